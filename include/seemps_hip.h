@@ -1,0 +1,198 @@
+/*
+ * seemps_hip.h -- C ABI of the MI355X (gfx950) library for applying a matrix
+ * product operator (MPO) to a matrix product state (MPS) and compressing the
+ * result with the two-site variational sweep.
+ *
+ * Paper: "SeeMPS" (arXiv 2601.16734).  Each entry point names the passage
+ * that defines its operation.
+ *
+ * Conventions shared by every call
+ *   - Tensors are real.  An MPS site tensor is A[k][chi_l][d][chi_r] and an MPO
+ *     site tensor is B[k][D_l][d_out][d_in][D_r], both dense C order, with open
+ *     ends (first and last bond dimension 1)  (Sec. 2.1, Sec. 2.2).
+ *   - Handles are opaque.  The caller owns every handle it receives and frees
+ *     it with the matching *_destroy call; the library owns the device memory
+ *     behind a handle.  Host pointers passed in are read during the call and
+ *     never retained.  Inputs are never modified.
+ *   - Every call returns an smps_status.  On failure nothing is written to
+ *     *out (it is set to NULL where it is a handle) and smps_last_error(ctx)
+ *     returns a message.  Nothing throws across this boundary.
+ *   - All device work is ordered on the stream given to smps_ctx_create.
+ *     Calls that return host values (scalars, shapes, reads) synchronise
+ *     that stream before returning.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef SEEMPS_HIP_H
+#define SEEMPS_HIP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct smps_ctx smps_ctx;
+typedef struct smps_mps smps_mps;
+typedef struct smps_mpo smps_mpo;
+
+typedef enum {
+    SMPS_OK = 0,
+    SMPS_EINVAL = -1,       /* bad argument: shapes do not chain, NULL handle, bad strategy */
+    SMPS_ENOMEM = -2,       /* device allocation failed or a workspace limit was exceeded */
+    SMPS_EHIP = -3,         /* a HIP runtime call failed */
+    SMPS_ENUMERIC = -4,     /* non-finite values met in a factorization */
+    SMPS_EUNSUPPORTED = -5  /* valid request this build does not handle */
+} smps_status;
+
+/* storage type of host data handed to *_create */
+enum { SMPS_F64 = 0, SMPS_F32 = 1 };
+
+/* arithmetic of the contractions; factorizations, discarded-weight sums and
+   norms are always FP64 */
+enum {
+    SMPS_PREC_FP64 = 0,    /* FP64 MFMA, FP64 accumulation */
+    SMPS_PREC_FP32 = 1,    /* FP32 MFMA, FP32 accumulation */
+    SMPS_PREC_BF16X3 = 2,  /* x = hi + lo in bf16, product hi*hi + hi*lo + lo*hi, FP32 accumulation */
+    SMPS_PREC_BF16 = 3     /* one bf16 product, FP32 accumulation */
+};
+
+/* truncation rule (Sec. 2.3) */
+enum {
+    SMPS_TRUNC_REL_NORM2 = 0,  /* smallest r >= 1 with sum_{j>=r} s_j^2 <= tol * sum_j s_j^2 */
+    SMPS_TRUNC_REL_SV = 1      /* keep s_j > tol * s_0 (at least one) */
+};
+
+/* factorization of the two-site tensor */
+enum {
+    SMPS_FACT_SVD = 0,        /* exact one-sided Jacobi SVD */
+    SMPS_FACT_RSVD_MLP = 1    /* randomized SVD sized by the rank predictor, exact SVD as fallback */
+};
+
+/* Compression strategy (Sec. 2.3): maximum bond, tolerance, rule, and the
+   number of sweeps of the variational search. */
+typedef struct {
+    int max_bond;      /* >= 1 */
+    double tol;        /* >= 0 */
+    int trunc_mode;    /* SMPS_TRUNC_* */
+    int max_sweeps;    /* >= 1; a sweep is a left-to-right and a right-to-left pass */
+    double sweep_tol;  /* 0: always run max_sweeps; > 0: stop once the relative change of
+                          ||psi||^2 over a sweep falls below it (one host sync per sweep) */
+    int precision;     /* SMPS_PREC_* */
+    int factorization; /* SMPS_FACT_* */
+} smps_strategy;
+
+/* Diagnostics of the last mpo_apply / simplify on a context. */
+typedef struct {
+    double error_bound;   /* sum over steps of sqrt(discarded weight): the accumulated
+                             truncation-error bound kept with the state (Sec. 2.3) */
+    double discarded;     /* sum over steps of the discarded weight */
+    double norm;          /* Frobenius norm of the result's centre tensor (FP64) */
+    int sweeps_done;
+    int steps;            /* two-site updates performed (site-updates) */
+    int rsvd_accepted;    /* randomized factorizations accepted */
+    int rsvd_fallbacks;   /* randomized factorizations replaced by the exact SVD */
+} smps_apply_info;
+
+/* ---- context ---------------------------------------------------------------
+ * device: HIP ordinal.  hip_stream: a hipStream_t (may be NULL for the null
+ * stream) on which all work of this context is enqueued; the caller keeps it
+ * alive for the lifetime of the context. */
+int smps_ctx_create(int device, void *hip_stream, smps_ctx **out);
+int smps_ctx_destroy(smps_ctx *ctx);
+const char *smps_last_error(const smps_ctx *ctx);
+/* Bytes of device workspace the context currently holds (grow-only arena). */
+int smps_ctx_workspace_bytes(const smps_ctx *ctx, size_t *bytes);
+
+/* ---- MPS (Sec. 2.1, Eq. general-MPS) ---------------------------------------
+ * L >= 1 sites; phys[L] local dimensions; bonds[L+1] with bonds[0] =
+ * bonds[L] = 1.  tensors[k] points to bonds[k]*phys[k]*bonds[k+1] host values
+ * of type dtype (C order); a NULL entry gives zeros.  Stored as FP64. */
+int smps_mps_create(smps_ctx *ctx, int L, const int *phys, const int *bonds, int dtype,
+                    const void *const *tensors, smps_mps **out);
+/* Same, from device memory: tensors[k] are device pointers of type dtype; the
+   data are copied on the context stream. */
+int smps_mps_create_device(smps_ctx *ctx, int L, const int *phys, const int *bonds, int dtype,
+                           const void *const *tensors, smps_mps **out);
+int smps_mps_destroy(smps_mps *mps);
+/* Shape query.  phys and bonds may be NULL; center = -1 unless the MPS is in
+   canonical form with that isometry centre (Sec. 2.3). */
+int smps_mps_shape(const smps_mps *mps, int *L, int *phys, int *bonds, int *center);
+/* Copy site tensor `site` (FP64, C order) into host_out; count must equal its size. */
+int smps_mps_read(smps_ctx *ctx, const smps_mps *mps, int site, double *host_out, size_t count);
+/* Device pointer of site tensor `site` (FP64, C order, owned by the handle). */
+int smps_mps_device_ptr(const smps_mps *mps, int site, const double **ptr);
+
+/* ---- MPO (Sec. 2.2, Eq. MPO) -------------------------------------------------
+ * phys_out[L], phys_in[L]; bonds[L+1] with ends 1; tensors[k] has
+ * bonds[k]*phys_out[k]*phys_in[k]*bonds[k+1] values [D_l][out][in][D_r]. */
+int smps_mpo_create(smps_ctx *ctx, int L, const int *phys_out, const int *phys_in, const int *bonds,
+                    int dtype, const void *const *tensors, smps_mpo **out);
+int smps_mpo_destroy(smps_mpo *mpo);
+
+/* ---- apply + compress (Sec. 2.4.2; Sec. 2.3 Eq. simplification; Sec. 2.5) ----
+ * Returns in *out a new MPS psi approximating U v: the minimiser of
+ * ||psi - U v||^2 over MPS with the strategy's bond limit, found by two-site
+ * sweeps from the guess v (right-canonicalised).  psi is canonical with centre
+ * 0 and is not normalised.  trunc_err (nullable) receives the accumulated
+ * error bound.  Validation: L equal, phys_in(U) == phys(v), strategy fields in
+ * range -> SMPS_EINVAL; non-finite two-site tensor -> SMPS_ENUMERIC. */
+int smps_mpo_apply(smps_ctx *ctx, const smps_mpo *U, const smps_mps *v, const smps_strategy *strategy,
+                   smps_mps **out, double *trunc_err);
+/* Compression of v itself (Eq. simplification with phi = v): identical to
+   smps_mpo_apply with the identity operator. */
+int smps_simplify(smps_ctx *ctx, const smps_mps *v, const smps_strategy *strategy,
+                  smps_mps **out, double *trunc_err);
+/* Diagnostics of the last apply/simplify call on ctx. */
+int smps_last_info(const smps_ctx *ctx, smps_apply_info *info);
+/* Per-step log of the last apply/simplify: for step i (in sweep order),
+   deltas[i] = discarded weight, ranks[i] = kept rank, spectra[i*32 + j] =
+   j-th largest singular value (0 beyond the rank of the two-site tensor).
+   Any pointer may be NULL; max_steps bounds the copy; *steps receives the
+   number of steps available. */
+int smps_last_log(const smps_ctx *ctx, int max_steps, double *deltas, int *ranks, double *spectra,
+                  int *steps);
+
+/* Batched apply: n independent (U[i], v[i]) problems of arbitrary length and
+   bonds under one strategy, advanced together bond step by bond step; the
+   launch sequence is captured once in a HIP graph per batch shape and replayed.
+   out[i] as for smps_mpo_apply; trunc_err (nullable) has n entries. */
+int smps_mpo_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
+                           const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+
+/* ---- scalar product and norm (Sec. 2.4.4) -------------------------------------
+ * scprod: <a, b> by the transfer-matrix sweep, O(L chi^3 d), FP64.
+ * norm: ||a|| -- from the centre tensor when a is canonical (O(d chi^2)),
+ * otherwise sqrt(scprod(a, a)). */
+int smps_scprod(smps_ctx *ctx, const smps_mps *a, const smps_mps *b, double *out);
+int smps_norm(smps_ctx *ctx, const smps_mps *a, double *out);
+
+/* ---- learned rank predictor for the randomized factorization ------------------
+ * A 32-64-64-1 ReLU network with bf16 weights (FP32 master copy, FP32
+ * accumulation).  Input: the 32 largest log(s_j / s_0) of a bond's spectrum in
+ * the previous sweep (padded with log(1e-30)); output: log of the kept rank.
+ * Training runs on the device with the library's own forward, backward and
+ * Adam kernels.
+ *   feats: n x 32 host floats; labels: n host floats (log rank).
+ *   smps_rank_mlp_init: seed the weights (deterministic in seed).
+ *   smps_rank_mlp_train: `epochs` passes of mini-batch Adam (batch, lr);
+ *       *final_loss receives the mean loss of the last epoch.
+ *   smps_rank_mlp_predict: out[n] = predicted log rank.
+ *   smps_rank_mlp_get / set: the FP32 master parameters in the order
+ *       W1[64x32], b1[64], W2[64x64], b2[64], W3[1x64], b3[1] (4353 floats). */
+int smps_rank_mlp_init(smps_ctx *ctx, unsigned long long seed);
+int smps_rank_mlp_train(smps_ctx *ctx, int n, const float *feats, const float *labels, int epochs, int batch,
+                        float lr, float *final_loss);
+int smps_rank_mlp_predict(smps_ctx *ctx, int n, const float *feats, float *out);
+int smps_rank_mlp_get(const smps_ctx *ctx, float *params, int count);
+int smps_rank_mlp_set(smps_ctx *ctx, const float *params, int count);
+/* One forward + backward of the loss on a host batch, returning the loss and
+   the gradient w.r.t. the FP32 master parameters (same order as _get); used to
+   check the hand-written backward kernels. */
+int smps_rank_mlp_grad(smps_ctx *ctx, int n, const float *feats, const float *labels, float *loss,
+                       float *grad, int count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEEMPS_HIP_H */

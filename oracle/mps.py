@@ -37,6 +37,22 @@ REL_NORM2 = 0
 REL_SV = 1
 
 
+def chain(spec: str, *ops):
+    """np.einsum(spec, *ops) evaluated by contracting the operands pairwise from
+    left to right (each pair through BLAS); the order of the operands in the
+    spec is the order of contraction."""
+    ins, out = spec.split("->")
+    terms = ins.split(",")
+    cur, cur_t = ops[0], terms[0]
+    for i in range(1, len(ops)):
+        nxt = terms[i]
+        later = set("".join(terms[i + 1:])) | set(out)
+        keep = "".join(ch for ch in dict.fromkeys(cur_t + nxt) if ch in later)
+        cur = np.einsum(f"{cur_t},{nxt}->{keep}", cur, ops[i], optimize=True)
+        cur_t = keep
+    return np.einsum(f"{cur_t}->{out}", cur)
+
+
 # ---------------------------------------------------------------------------
 # Scalar product and norm (Sec. 2.4.4)
 # ---------------------------------------------------------------------------
@@ -45,7 +61,7 @@ def scprod(a, b) -> float:
     """<a, b> by the transfer-matrix sweep E_{k+1} = sum E_k a_k b_k, O(L chi^3 d)."""
     E = np.ones((1, 1))
     for A, B in zip(a, b):
-        E = np.einsum("ab,asc,bsd->cd", E, A.conj(), B)
+        E = chain("ab,asc,bsd->cd", E, A.conj(), B)
     return float(E[0, 0].real) if np.isrealobj(E) else E[0, 0]
 
 
@@ -203,10 +219,10 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
     Renv[L] = one
 
     def grow_left(E, P, Bk, Ak):
-        return np.einsum("abx,asc,bspd,xpy->cdy", E, P, Bk, Ak, optimize=True)
+        return chain("abx,asc,bspd,xpy->cdy", E, P, Bk, Ak)
 
     def grow_right(E, P, Bk, Ak):
-        return np.einsum("cdy,asc,bspd,xpy->abx", E, P, Bk, Ak, optimize=True)
+        return chain("cdy,asc,bspd,xpy->abx", E, P, Bk, Ak)
 
     for k in range(L - 1, 0, -1):
         Renv[k] = grow_right(Renv[k + 1], psi[k], B[k], A[k])
@@ -220,8 +236,8 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
         return res
 
     def theta_at(k):
-        return np.einsum("abx,xpy,bspe,yqz,etqf,cfz->astc",
-                         Lenv[k], A[k], B[k], A[k + 1], B[k + 1], Renv[k + 2], optimize=True)
+        return chain("abx,xpy,bspe,yqz,etqf,cfz->astc",
+                     Lenv[k], A[k], B[k], A[k + 1], B[k + 1], Renv[k + 2])
 
     for sw in range(sweeps):
         for direction, bonds in ((+1, range(0, L - 1)), (-1, range(L - 2, -1, -1))):
@@ -257,21 +273,21 @@ def apply_simplify_explicit(mpo, mps, max_bond: int, tol: float, sweeps: int = 4
     Lenv[0] = np.ones((1, 1))
     Renv[L] = np.ones((1, 1))
     for k in range(L - 1, 0, -1):
-        Renv[k] = np.einsum("cg,asc,hsg->ah", Renv[k + 1], psi[k], C[k])
+        Renv[k] = chain("cg,asc,hsg->ah", Renv[k + 1], psi[k], C[k])
     res = SweepResult(mps=psi, norm=0.0, ranks=[])
     for sw in range(sweeps):
         for direction, bonds in ((+1, range(0, L - 1)), (-1, range(L - 2, -1, -1))):
             for k in bonds:
-                th = np.einsum("ag,gsh,hti,ci->astc", Lenv[k], C[k], C[k + 1], Renv[k + 2])
+                th = chain("ag,gsh,hti,ci->astc", Lenv[k], C[k], C[k + 1], Renv[k + 2])
                 a, s, t, c = th.shape
                 left, right, r, delta, S = _split(th, a, s, t, c, tol, max_bond, mode, direction)
                 psi[k], psi[k + 1] = left, right
                 res.deltas.append(delta)
                 res.norms2.append(float(np.sum(S[:r] ** 2)))
                 if direction > 0:
-                    Lenv[k + 1] = np.einsum("ag,asc,gsh->ch", Lenv[k], psi[k], C[k])
+                    Lenv[k + 1] = chain("ag,asc,gsh->ch", Lenv[k], psi[k], C[k])
                 else:
-                    Renv[k + 1] = np.einsum("cg,asc,hsg->ah", Renv[k + 2], psi[k + 1], C[k + 1])
+                    Renv[k + 1] = chain("cg,asc,hsg->ah", Renv[k + 2], psi[k + 1], C[k + 1])
     res.mps = psi
     res.norm = norm_from_center(psi, 0)
     res.ranks = [1] + [p.shape[2] for p in psi]

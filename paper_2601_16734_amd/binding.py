@@ -1,0 +1,353 @@
+"""Thin ctypes binding of libseemps_hip.so (include/seemps_hip.h).
+
+Argument marshalling only: every step of apply/compress, scalar product and
+norm runs in the library's HIP kernels.  PyTorch is used, when present, only
+to obtain the current HIP stream (and device buffers for *_create_device).
+Loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int, c_size_t, c_ulonglong, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libseemps_hip.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "bf16": PREC_BF16}
+TRUNC_REL_NORM2, TRUNC_REL_SV = 0, 1
+FACT_SVD, FACT_RSVD_MLP = 0, 1
+MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
+
+# every symbol the header declares, in declaration order
+EXPORTS = [
+    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes",
+    "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
+    "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
+    "smps_last_info", "smps_last_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
+    "smps_rank_mlp_set", "smps_rank_mlp_grad",
+]
+
+
+class Strategy(ctypes.Structure):
+    _fields_ = [("max_bond", c_int), ("tol", c_double), ("trunc_mode", c_int), ("max_sweeps", c_int),
+                ("sweep_tol", c_double), ("precision", c_int), ("factorization", c_int)]
+
+
+class ApplyInfo(ctypes.Structure):
+    _fields_ = [("error_bound", c_double), ("discarded", c_double), ("norm", c_double), ("sweeps_done", c_int),
+                ("steps", c_int), ("rsvd_accepted", c_int), ("rsvd_fallbacks", c_int)]
+
+
+class SmpsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load the library (once).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    vp, ip, dp = c_void_p, POINTER(c_int), POINTER(c_double)
+    sig = {
+        "smps_ctx_create": (c_int, [c_int, vp, POINTER(vp)]),
+        "smps_ctx_destroy": (c_int, [vp]),
+        "smps_last_error": (ctypes.c_char_p, [vp]),
+        "smps_ctx_workspace_bytes": (c_int, [vp, POINTER(c_size_t)]),
+        "smps_mps_create": (c_int, [vp, c_int, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
+        "smps_mps_create_device": (c_int, [vp, c_int, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
+        "smps_mps_destroy": (c_int, [vp]),
+        "smps_mps_shape": (c_int, [vp, ip, ip, ip, ip]),
+        "smps_mps_read": (c_int, [vp, vp, c_int, dp, c_size_t]),
+        "smps_mps_device_ptr": (c_int, [vp, c_int, POINTER(vp)]),
+        "smps_mpo_create": (c_int, [vp, c_int, ip, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
+        "smps_mpo_destroy": (c_int, [vp]),
+        "smps_mpo_apply": (c_int, [vp, vp, vp, POINTER(Strategy), POINTER(vp), dp]),
+        "smps_simplify": (c_int, [vp, vp, POINTER(Strategy), POINTER(vp), dp]),
+        "smps_last_info": (c_int, [vp, POINTER(ApplyInfo)]),
+        "smps_last_log": (c_int, [vp, c_int, dp, ip, dp, ip]),
+        "smps_mpo_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
+        "smps_scprod": (c_int, [vp, vp, vp, dp]),
+        "smps_norm": (c_int, [vp, vp, dp]),
+        "smps_rank_mlp_init": (c_int, [vp, c_ulonglong]),
+        "smps_rank_mlp_train": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), c_int, c_int, c_float,
+                                        POINTER(c_float)]),
+        "smps_rank_mlp_predict": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float)]),
+        "smps_rank_mlp_get": (c_int, [vp, POINTER(c_float), c_int]),
+        "smps_rank_mlp_set": (c_int, [vp, POINTER(c_float), c_int]),
+        "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
+                                       POINTER(c_float), c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strategy(max_bond: int, tol: float, *, sweeps: int = 4, precision="fp64", trunc_mode: int = TRUNC_REL_NORM2,
+             sweep_tol: float = 0.0, factorization: int = FACT_SVD) -> Strategy:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Strategy(int(max_bond), float(tol), int(trunc_mode), int(sweeps), float(sweep_tol), prec, int(factorization))
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_float))
+
+
+class MPS:
+    """Handle of a device MPS (owned; freed on destroy / garbage collection)."""
+
+    def __init__(self, ctx: "Context", handle: c_void_p):
+        self.ctx = ctx
+        self.h = handle
+
+    def shape(self):
+        L = c_int()
+        self.ctx.lib.smps_mps_shape(self.h, byref(L), None, None, None)
+        phys = (c_int * L.value)()
+        bonds = (c_int * (L.value + 1))()
+        center = c_int()
+        self.ctx.lib.smps_mps_shape(self.h, None, phys, bonds, byref(center))
+        return list(phys), list(bonds), center.value
+
+    def read(self) -> list[np.ndarray]:
+        phys, bonds, _ = self.shape()
+        out = []
+        for k in range(len(phys)):
+            a = np.empty((bonds[k], phys[k], bonds[k + 1]), dtype=np.float64)
+            self.ctx._check(self.ctx.lib.smps_mps_read(self.ctx.h, self.h, k, a.ctypes.data_as(POINTER(c_double)),
+                                                      a.size))
+            out.append(a)
+        return out
+
+    def device_ptr(self, site: int) -> int:
+        p = c_void_p()
+        self.ctx._check(self.ctx.lib.smps_mps_device_ptr(self.h, site, byref(p)))
+        return p.value
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.smps_mps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                self.destroy()
+        except Exception:
+            pass
+
+
+class MPO:
+    def __init__(self, ctx: "Context", handle: c_void_p, L: int):
+        self.ctx = ctx
+        self.h = handle
+        self.L = L
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.smps_mpo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                self.destroy()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context bound to one device and one HIP stream (torch's
+    current stream by default)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        self.lib = load()
+        if stream is None:
+            import torch
+            torch.cuda.set_device(device)
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = c_void_p()
+        rc = self.lib.smps_ctx_create(int(device), c_void_p(stream), byref(h))
+        if rc != OK:
+            raise SmpsError(rc, f"smps_ctx_create(device={device}) failed")
+        self.h = h
+        self.device = device
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise SmpsError(rc, self.lib.smps_last_error(self.h).decode())
+
+    def close(self):
+        if self.h:
+            self.lib.smps_ctx_destroy(self.h)
+            self.h = None
+
+    # ---- handles
+    def mps_create(self, tensors, dtype=np.float64) -> MPS:
+        arrs = [np.ascontiguousarray(t, dtype=dtype) for t in tensors]
+        L = len(arrs)
+        phys = (c_int * L)(*[a.shape[1] for a in arrs])
+        bonds = (c_int * (L + 1))(*([a.shape[0] for a in arrs] + [arrs[-1].shape[2]]))
+        ptrs = (c_void_p * L)(*[a.ctypes.data for a in arrs])
+        h = c_void_p()
+        self._check(self.lib.smps_mps_create(self.h, L, phys, bonds, F64 if dtype == np.float64 else F32, ptrs,
+                                             byref(h)))
+        return MPS(self, h)
+
+    def mps_create_device(self, tensors) -> MPS:
+        """From torch device tensors (float64 or float32), copied on the stream."""
+        import torch
+        L = len(tensors)
+        dt = F64 if tensors[0].dtype == torch.float64 else F32
+        ts = [t.contiguous() for t in tensors]
+        phys = (c_int * L)(*[t.shape[1] for t in ts])
+        bonds = (c_int * (L + 1))(*([t.shape[0] for t in ts] + [ts[-1].shape[2]]))
+        ptrs = (c_void_p * L)(*[t.data_ptr() for t in ts])
+        h = c_void_p()
+        self._check(self.lib.smps_mps_create_device(self.h, L, phys, bonds, dt, ptrs, byref(h)))
+        return MPS(self, h)
+
+    def mpo_create(self, tensors, dtype=np.float64) -> MPO:
+        arrs = [np.ascontiguousarray(t, dtype=dtype) for t in tensors]
+        L = len(arrs)
+        pout = (c_int * L)(*[a.shape[1] for a in arrs])
+        pin = (c_int * L)(*[a.shape[2] for a in arrs])
+        bonds = (c_int * (L + 1))(*([a.shape[0] for a in arrs] + [arrs[-1].shape[3]]))
+        ptrs = (c_void_p * L)(*[a.ctypes.data for a in arrs])
+        h = c_void_p()
+        self._check(self.lib.smps_mpo_create(self.h, L, pout, pin, bonds, F64 if dtype == np.float64 else F32, ptrs,
+                                             byref(h)))
+        return MPO(self, h, L)
+
+    # ---- the hot path
+    def mpo_apply(self, U: MPO, v: MPS, st: Strategy):
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_mpo_apply(self.h, U.h, v.h, byref(st), byref(out), byref(err)))
+        return MPS(self, out), err.value
+
+    def simplify(self, v: MPS, st: Strategy):
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_simplify(self.h, v.h, byref(st), byref(out), byref(err)))
+        return MPS(self, out), err.value
+
+    def mpo_apply_batched(self, Us, vs, st: Strategy):
+        n = len(vs)
+        uh = (c_void_p * n)(*[u.h for u in Us])
+        vh = (c_void_p * n)(*[v.h for v in vs])
+        outs = (c_void_p * n)()
+        errs = (c_double * n)()
+        self._check(self.lib.smps_mpo_apply_batched(self.h, n, uh, vh, byref(st), outs, errs))
+        return [MPS(self, c_void_p(outs[i])) for i in range(n)], list(errs)
+
+    def scprod(self, a: MPS, b: MPS) -> float:
+        r = c_double()
+        self._check(self.lib.smps_scprod(self.h, a.h, b.h, byref(r)))
+        return r.value
+
+    def norm(self, a: MPS) -> float:
+        r = c_double()
+        self._check(self.lib.smps_norm(self.h, a.h, byref(r)))
+        return r.value
+
+    def last_info(self) -> dict:
+        info = ApplyInfo()
+        self._check(self.lib.smps_last_info(self.h, byref(info)))
+        return {f: getattr(info, f) for f, _ in ApplyInfo._fields_}
+
+    def last_log(self):
+        n = c_int()
+        self._check(self.lib.smps_last_log(self.h, 0, None, None, None, byref(n)))
+        m = n.value
+        deltas = np.zeros(m)
+        ranks = np.zeros(m, dtype=np.int32)
+        spec = np.zeros((m, 32))
+        self._check(self.lib.smps_last_log(self.h, m, deltas.ctypes.data_as(POINTER(c_double)),
+                                           ranks.ctypes.data_as(POINTER(c_int)),
+                                           spec.ctypes.data_as(POINTER(c_double)), byref(n)))
+        return deltas, ranks, spec
+
+    def workspace_bytes(self) -> int:
+        b = c_size_t()
+        self._check(self.lib.smps_ctx_workspace_bytes(self.h, byref(b)))
+        return b.value
+
+    # ---- rank predictor
+    def rank_mlp_init(self, seed: int = 0):
+        self._check(self.lib.smps_rank_mlp_init(self.h, c_ulonglong(seed)))
+
+    def rank_mlp_train(self, feats, labels, epochs: int, batch: int, lr: float) -> float:
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        loss = c_float()
+        self._check(self.lib.smps_rank_mlp_train(self.h, len(y), _fptr(f), _fptr(y), int(epochs), int(batch),
+                                                 float(lr), byref(loss)))
+        return loss.value
+
+    def rank_mlp_predict(self, feats) -> np.ndarray:
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        out = np.zeros(f.shape[0], dtype=np.float32)
+        self._check(self.lib.smps_rank_mlp_predict(self.h, f.shape[0], _fptr(f), _fptr(out)))
+        return out
+
+    def rank_mlp_get(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.smps_rank_mlp_get(self.h, _fptr(p), MLP_PARAMS))
+        return p
+
+    def rank_mlp_set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(self.lib.smps_rank_mlp_set(self.h, _fptr(p), p.size))
+
+    def rank_mlp_grad(self, feats, labels):
+        f = np.ascontiguousarray(feats, dtype=np.float32)
+        y = np.ascontiguousarray(labels, dtype=np.float32)
+        loss = c_float()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._check(self.lib.smps_rank_mlp_grad(self.h, len(y), _fptr(f), _fptr(y), byref(loss), _fptr(g), g.size))
+        return loss.value, g
+
+
+# names of the boundary, as module-level calls on a context
+def mps_create(ctx: Context, tensors, dtype=np.float64) -> MPS:
+    return ctx.mps_create(tensors, dtype)
+
+
+def mpo_create(ctx: Context, tensors, dtype=np.float64) -> MPO:
+    return ctx.mpo_create(tensors, dtype)
+
+
+def mpo_apply(ctx: Context, U: MPO, v: MPS, st: Strategy):
+    return ctx.mpo_apply(U, v, st)
+
+
+def simplify(ctx: Context, v: MPS, st: Strategy):
+    return ctx.simplify(v, st)
+
+
+def scprod(ctx: Context, a: MPS, b: MPS) -> float:
+    return ctx.scprod(a, b)
+
+
+def norm(ctx: Context, a: MPS) -> float:
+    return ctx.norm(a)

@@ -1,0 +1,453 @@
+// C ABI entry points: context, handles, validation, scalar product and norm.
+
+#include <cmath>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace smps {
+
+int fail(smps_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+void* dev_alloc(smps_ctx* c, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    auto it = c->pool.find(bytes);
+    if (it != c->pool.end()) {
+        void* p = it->second;
+        c->pool.erase(it);
+        return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_release(smps_ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    if (bytes == 0) bytes = 8;
+    c->pool.emplace(bytes, p);
+}
+
+int ensure_arena(smps_ctx* c, size_t bytes) {
+    if (bytes <= c->arena_bytes) return SMPS_OK;
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->arena) hipFree(c->arena);
+    c->arena = nullptr;
+    c->arena_bytes = 0;
+    size_t want = bytes + bytes / 8;
+    if (hipMalloc((void**)&c->arena, want) != hipSuccess) {
+        c->arena = nullptr;
+        return fail(c, SMPS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    c->arena_bytes = want;
+    return SMPS_OK;
+}
+
+int ensure_pinned(smps_ctx* c, size_t bytes) {
+    if (bytes <= c->pinned_bytes) return SMPS_OK;
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->pinned) hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    SMPS_HIP(c, hipHostMalloc((void**)&c->pinned, bytes, hipHostMallocDefault));
+    c->pinned_bytes = bytes;
+    return SMPS_OK;
+}
+
+smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds) {
+    smps_mps* m = new smps_mps();
+    m->ctx = c;
+    m->L = L;
+    m->phys = phys;
+    m->bonds = bonds;
+    m->off.resize(L);
+    size_t tot = 0;
+    for (int k = 0; k < L; ++k) {
+        m->off[k] = tot;
+        tot += m->site_size(k);
+    }
+    m->bytes = 8 * tot;
+    m->data = (double*)dev_alloc(c, m->bytes);
+    if (!m->data) {
+        delete m;
+        return nullptr;
+    }
+    return m;
+}
+
+static int check_strategy(smps_ctx* c, const smps_strategy* st) {
+    if (!st) return fail(c, SMPS_EINVAL, "strategy is NULL");
+    if (st->max_bond < 1) return fail(c, SMPS_EINVAL, "max_bond must be >= 1");
+    if (!(st->tol >= 0.0) || !std::isfinite(st->tol)) return fail(c, SMPS_EINVAL, "tol must be finite and >= 0");
+    if (st->max_sweeps < 1) return fail(c, SMPS_EINVAL, "max_sweeps must be >= 1");
+    if (st->trunc_mode != SMPS_TRUNC_REL_NORM2 && st->trunc_mode != SMPS_TRUNC_REL_SV)
+        return fail(c, SMPS_EINVAL, "unknown truncation mode");
+    if (st->precision < SMPS_PREC_FP64 || st->precision > SMPS_PREC_BF16)
+        return fail(c, SMPS_EINVAL, "unknown precision");
+    if (st->factorization != SMPS_FACT_SVD && st->factorization != SMPS_FACT_RSVD_MLP)
+        return fail(c, SMPS_EINVAL, "unknown factorization");
+    return SMPS_OK;
+}
+
+static int check_chain(smps_ctx* c, int L, const int* phys, const int* bonds) {
+    if (L < 1) return fail(c, SMPS_EINVAL, "L must be >= 1");
+    if (!phys || !bonds) return fail(c, SMPS_EINVAL, "phys/bonds is NULL");
+    if (bonds[0] != 1 || bonds[L] != 1) return fail(c, SMPS_EINVAL, "open boundary bonds must be 1");
+    for (int k = 0; k < L; ++k)
+        if (phys[k] < 1) return fail(c, SMPS_EINVAL, "physical dimensions must be >= 1");
+    for (int k = 0; k <= L; ++k)
+        if (bonds[k] < 1) return fail(c, SMPS_EINVAL, "bond dimensions must be >= 1");
+    return SMPS_OK;
+}
+
+}  // namespace smps
+
+using namespace smps;
+
+extern "C" {
+
+int smps_ctx_create(int device, void* hip_stream, smps_ctx** out) {
+    if (!out) return SMPS_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SMPS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SMPS_EHIP;
+    if (jacobi_init(device) != hipSuccess) return SMPS_EHIP;
+    smps_ctx* c = new smps_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return SMPS_OK;
+}
+
+int smps_ctx_destroy(smps_ctx* c) {
+    if (!c) return SMPS_EINVAL;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    if (c->arena) hipFree(c->arena);
+    if (c->pinned) hipHostFree(c->pinned);
+    for (auto& kv : c->pool) hipFree(kv.second);
+    mlp_free(c);
+    delete c;
+    return SMPS_OK;
+}
+
+const char* smps_last_error(const smps_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+int smps_ctx_workspace_bytes(const smps_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return SMPS_EINVAL;
+    *bytes = c->arena_bytes;
+    return SMPS_OK;
+}
+
+static int mps_create_impl(smps_ctx* c, int L, const int* phys, const int* bonds, int dtype,
+                           const void* const* tensors, smps_mps** out, bool device) {
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return SMPS_EINVAL;
+    int rc = check_chain(c, L, phys, bonds);
+    if (rc) return rc;
+    if (dtype != SMPS_F64 && dtype != SMPS_F32) return fail(c, SMPS_EINVAL, "unknown dtype");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    smps_mps* m = new_mps(c, L, std::vector<int>(phys, phys + L), std::vector<int>(bonds, bonds + L + 1));
+    if (!m) return fail(c, SMPS_ENOMEM, "MPS allocation failed");
+    std::vector<double> tmp;
+    for (int k = 0; k < L; ++k) {
+        const size_t n = m->site_size(k);
+        double* dst = m->data + m->off[k];
+        const void* src = tensors ? tensors[k] : nullptr;
+        hipError_t e = hipSuccess;
+        if (!src) {
+            e = launch_fill(dst, 0.0, n, c->stream);
+        } else if (device) {
+            if (dtype == SMPS_F64)
+                e = hipMemcpyAsync(dst, src, 8 * n, hipMemcpyDeviceToDevice, c->stream);
+            else
+                e = launch_convert_f32_f64((const float*)src, dst, n, c->stream);
+        } else {
+            if (dtype == SMPS_F64) {
+                e = hipMemcpyAsync(dst, src, 8 * n, hipMemcpyHostToDevice, c->stream);
+            } else {
+                tmp.resize(n);
+                const float* f = (const float*)src;
+                for (size_t i = 0; i < n; ++i) tmp[i] = (double)f[i];
+                e = hipMemcpyAsync(dst, tmp.data(), 8 * n, hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            }
+        }
+        if (e != hipSuccess) {
+            smps_mps_destroy(m);
+            return fail(c, SMPS_EHIP, std::string("MPS upload failed: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        smps_mps_destroy(m);
+        return fail(c, SMPS_EHIP, std::string("MPS upload failed: ") + hipGetErrorString(e));
+    }
+    *out = m;
+    return SMPS_OK;
+}
+
+int smps_mps_create(smps_ctx* c, int L, const int* phys, const int* bonds, int dtype, const void* const* tensors,
+                    smps_mps** out) {
+    return mps_create_impl(c, L, phys, bonds, dtype, tensors, out, false);
+}
+
+int smps_mps_create_device(smps_ctx* c, int L, const int* phys, const int* bonds, int dtype,
+                           const void* const* tensors, smps_mps** out) {
+    return mps_create_impl(c, L, phys, bonds, dtype, tensors, out, true);
+}
+
+int smps_mps_destroy(smps_mps* m) {
+    if (!m) return SMPS_EINVAL;
+    if (m->ctx) dev_release(m->ctx, m->data, m->bytes);
+    m->data = nullptr;
+    delete m;
+    return SMPS_OK;
+}
+
+int smps_mps_shape(const smps_mps* m, int* L, int* phys, int* bonds, int* center) {
+    if (!m) return SMPS_EINVAL;
+    if (L) *L = m->L;
+    if (phys) std::memcpy(phys, m->phys.data(), sizeof(int) * m->L);
+    if (bonds) std::memcpy(bonds, m->bonds.data(), sizeof(int) * (m->L + 1));
+    if (center) *center = m->center;
+    return SMPS_OK;
+}
+
+int smps_mps_read(smps_ctx* c, const smps_mps* m, int site, double* host_out, size_t count) {
+    if (!c) return SMPS_EINVAL;
+    if (!m || !host_out) return fail(c, SMPS_EINVAL, "NULL argument");
+    if (site < 0 || site >= m->L) return fail(c, SMPS_EINVAL, "site out of range");
+    if (count != m->site_size(site)) return fail(c, SMPS_EINVAL, "count does not match the site size");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    SMPS_HIP(c, hipMemcpyAsync(host_out, m->data + m->off[site], 8 * count, hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    return SMPS_OK;
+}
+
+int smps_mps_device_ptr(const smps_mps* m, int site, const double** ptr) {
+    if (!m || !ptr || site < 0 || site >= m->L) return SMPS_EINVAL;
+    *ptr = m->data + m->off[site];
+    return SMPS_OK;
+}
+
+int smps_mpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const int* bonds, int dtype,
+                    const void* const* tensors, smps_mpo** out) {
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return SMPS_EINVAL;
+    int rc = check_chain(c, L, pout, bonds);
+    if (rc) return rc;
+    rc = check_chain(c, L, pin, bonds);
+    if (rc) return rc;
+    if (dtype != SMPS_F64 && dtype != SMPS_F32) return fail(c, SMPS_EINVAL, "unknown dtype");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    smps_mpo* u = new smps_mpo();
+    u->ctx = c;
+    u->L = L;
+    u->pout.assign(pout, pout + L);
+    u->pin.assign(pin, pin + L);
+    u->bonds.assign(bonds, bonds + L + 1);
+    u->off.resize(L);
+    size_t tot = 0;
+    for (int k = 0; k < L; ++k) {
+        u->off[k] = tot;
+        tot += u->site_size(k);
+    }
+    u->bytes = 8 * tot;
+    u->data = (double*)dev_alloc(c, u->bytes);
+    if (!u->data) {
+        delete u;
+        return fail(c, SMPS_ENOMEM, "MPO allocation failed");
+    }
+    std::vector<double> h(tot, 0.0);
+    for (int k = 0; k < L; ++k) {
+        const void* src = tensors ? tensors[k] : nullptr;
+        if (!src) continue;
+        const size_t n = u->site_size(k);
+        if (dtype == SMPS_F64)
+            std::memcpy(h.data() + u->off[k], src, 8 * n);
+        else
+            for (size_t i = 0; i < n; ++i) h[u->off[k] + i] = ((const float*)src)[i];
+    }
+    hipError_t e = hipMemcpyAsync(u->data, h.data(), 8 * tot, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        smps_mpo_destroy(u);
+        return fail(c, SMPS_EHIP, std::string("MPO upload failed: ") + hipGetErrorString(e));
+    }
+    *out = u;
+    return SMPS_OK;
+}
+
+int smps_mpo_destroy(smps_mpo* u) {
+    if (!u) return SMPS_EINVAL;
+    if (u->ctx) dev_release(u->ctx, u->data, u->bytes);
+    delete u;
+    return SMPS_OK;
+}
+
+static int check_pair(smps_ctx* c, const smps_mpo* U, const smps_mps* v) {
+    if (!U || !v) return fail(c, SMPS_EINVAL, "NULL handle");
+    if (U->L != v->L) return fail(c, SMPS_EINVAL, "MPO and MPS lengths differ");
+    for (int k = 0; k < v->L; ++k)
+        if (U->pin[k] != v->phys[k]) return fail(c, SMPS_EINVAL, "MPO input dimension differs from MPS physical dimension");
+    for (int k = 0; k < v->L; ++k)
+        if (U->pout[k] != U->pin[k])
+            return fail(c, SMPS_EUNSUPPORTED, "the guess is the input state, so the operator must map each site "
+                                              "space to itself (phys_out == phys_in)");
+    return SMPS_OK;
+}
+
+int smps_mpo_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy* st, smps_mps** out,
+                   double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_pair(c, U, v);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
+    if (rc) return rc;
+    SMPS_HIP(c, hipSetDevice(c->device));
+    return run_apply(c, U, v, *st, out, trunc_err);
+}
+
+int smps_simplify(smps_ctx* c, const smps_mps* v, const smps_strategy* st, smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!v) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    // identity operator with bond 1 (Eq. simplification with phi = v)
+    std::vector<int> bonds(v->L + 1, 1);
+    std::vector<std::vector<double>> eye(v->L);
+    std::vector<const void*> ptrs(v->L);
+    for (int k = 0; k < v->L; ++k) {
+        const int d = v->phys[k];
+        eye[k].assign((size_t)d * d, 0.0);
+        for (int i = 0; i < d; ++i) eye[k][(size_t)i * d + i] = 1.0;
+        ptrs[k] = eye[k].data();
+    }
+    smps_mpo* I = nullptr;
+    rc = smps_mpo_create(c, v->L, v->phys.data(), v->phys.data(), bonds.data(), SMPS_F64, ptrs.data(), &I);
+    if (rc) return rc;
+    rc = run_apply(c, I, v, *st, out, trunc_err);
+    smps_mpo_destroy(I);
+    return rc;
+}
+
+int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                           const smps_strategy* st, smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (n < 0 || (n > 0 && (!U || !v || !out))) return fail(c, SMPS_EINVAL, "bad batch arguments");
+    for (int i = 0; i < n; ++i) out[i] = nullptr;
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = check_pair(c, U[i], v[i]);
+        if (rc) return rc;
+    }
+    SMPS_HIP(c, hipSetDevice(c->device));
+    return run_apply_batched(c, n, U, v, *st, out, trunc_err);
+}
+
+int smps_last_info(const smps_ctx* c, smps_apply_info* info) {
+    if (!c || !info) return SMPS_EINVAL;
+    *info = c->info;
+    return SMPS_OK;
+}
+
+int smps_last_log(const smps_ctx* c, int max_steps, double* deltas, int* ranks, double* spectra, int* steps) {
+    if (!c) return SMPS_EINVAL;
+    const int n = (int)c->log_delta.size();
+    if (steps) *steps = n;
+    const int m = std::min(n, std::max(0, max_steps));
+    if (deltas) std::memcpy(deltas, c->log_delta.data(), sizeof(double) * m);
+    if (ranks) std::memcpy(ranks, c->log_rank.data(), sizeof(int) * m);
+    if (spectra) std::memcpy(spectra, c->log_spec.data(), sizeof(double) * 32 * (size_t)m);
+    return SMPS_OK;
+}
+
+// <a, b> by the transfer matrix E_{k+1} = a_k^T (E_k b_k)  (Sec. 2.4.4)
+int smps_scprod(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out) {
+    if (!c) return SMPS_EINVAL;
+    if (!a || !b || !out) return fail(c, SMPS_EINVAL, "NULL argument");
+    if (a->L != b->L) return fail(c, SMPS_EINVAL, "lengths differ");
+    for (int k = 0; k < a->L; ++k)
+        if (a->phys[k] != b->phys[k]) return fail(c, SMPS_EINVAL, "physical dimensions differ");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    size_t maxE = 1, maxF = 1;
+    for (int k = 0; k < a->L; ++k) {
+        maxE = std::max(maxE, (size_t)a->bonds[k + 1] * b->bonds[k + 1]);
+        maxF = std::max(maxF, (size_t)a->bonds[k] * a->phys[k] * b->bonds[k + 1]);
+    }
+    const size_t oE0 = 0, oE1 = (8 * maxE + 255) / 256 * 256, oF = 2 * oE1, tot = oF + 8 * maxF + 256;
+    int rc = ensure_arena(c, tot);
+    if (rc) return rc;
+    double* E0 = (double*)(c->arena + oE0);
+    double* E1 = (double*)(c->arena + oE1);
+    double* F = (double*)(c->arena + oF);
+    SMPS_HIP(c, launch_fill(E0, 1.0, 1, c->stream));
+    for (int k = 0; k < a->L; ++k) {
+        const int ca = a->bonds[k], cb = b->bonds[k], d = a->phys[k], ca2 = a->bonds[k + 1], cb2 = b->bonds[k + 1];
+        GemmDesc g{};
+        g.dims = nullptr;
+        g.alpha = 1.0;
+        // F = E b_k : (ca x cb)(cb x d cb2)
+        g.A = E0;
+        g.B = b->data + b->off[k];
+        g.C = F;
+        g.M = dconst(ca);
+        g.N = dconst(d * cb2);
+        g.K = dconst(cb);
+        SMPS_HIP(c, launch_gemm(g, ca, d * cb2, 1, c->stream, P_F64));
+        // E' = a_k^T F : a_k stored (ca d) x ca2
+        GemmDesc h{};
+        h.alpha = 1.0;
+        h.A = a->data + a->off[k];
+        h.B = F;
+        h.C = E1;
+        h.M = dconst(ca2);
+        h.N = dconst(cb2);
+        h.K = dconst(ca * d);
+        h.ta = 1;
+        SMPS_HIP(c, launch_gemm(h, ca2, cb2, 1, c->stream, P_F64));
+        std::swap(E0, E1);
+    }
+    double r = 0.0;
+    SMPS_HIP(c, hipMemcpyAsync(&r, E0, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    *out = r;
+    return SMPS_OK;
+}
+
+int smps_norm(smps_ctx* c, const smps_mps* a, double* out) {
+    if (!c) return SMPS_EINVAL;
+    if (!a || !out) return fail(c, SMPS_EINVAL, "NULL argument");
+    if (a->center < 0) {
+        double s = 0.0;
+        int rc = smps_scprod(c, a, a, &s);
+        if (rc) return rc;
+        *out = std::sqrt(std::max(0.0, s));
+        return SMPS_OK;
+    }
+    SMPS_HIP(c, hipSetDevice(c->device));
+    int rc = ensure_arena(c, 256);
+    if (rc) return rc;
+    double* acc = (double*)c->arena;
+    const int n = (int)a->site_size(a->center);
+    SMPS_HIP(c, launch_sumsq(a->data + a->off[a->center], nullptr, dconst(n), n, acc, c->stream));
+    double r = 0.0;
+    SMPS_HIP(c, hipMemcpyAsync(&r, acc, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    *out = std::sqrt(r);
+    return SMPS_OK;
+}
+
+}  // extern "C"

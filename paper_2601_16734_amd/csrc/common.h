@@ -1,0 +1,118 @@
+// Internal definitions shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "seemps_hip.h"
+
+namespace smps {
+
+// A dimension known only on the device: value = mul * dims[idx] (idx < 0: value = mul).
+// Bond dimensions chosen by truncation live in a device array so that the
+// whole sweep can be enqueued (and captured) without reading ranks back.
+struct DimExpr {
+    int idx;
+    int mul;
+};
+
+__host__ __device__ inline DimExpr dconst(int v) { return DimExpr{-1, v}; }
+__host__ __device__ inline DimExpr ddyn(int idx, int mul = 1) { return DimExpr{idx, mul}; }
+
+__device__ __forceinline__ int eval_dim(const int* dims, DimExpr e) {
+    return e.idx < 0 ? e.mul : e.mul * dims[e.idx];
+}
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16 = 3 };
+enum DType { T_F64 = 0, T_F32 = 1 };
+
+// C[M x N] = alpha * op(A) op(B); A is M x K (K x M stored if ta), B is K x N
+// (N x K stored if tb), all compact row-major; C written N x M if tc.
+struct GemmDesc {
+    const void* A;
+    const void* B;
+    void* C;
+    const int* dims;
+    DimExpr M, N, K;
+    int ta, tb, tc;
+    int a_type, b_type, c_type;  // DType
+    double alpha;
+    // batching: pointer strides in elements per blockIdx.z (0 for unbatched)
+    long long sA, sB, sC;
+};
+
+// Small-K contraction with an MPO site tensor B[Dl][e][d][Dr] (see mpo_kernels).
+struct LeftMpoDesc {   // Y[a][t][b'][y] = sum_{b,q} X[a][b][q][y] * B[b][t][q][b']
+    const void* X;
+    void* Y;
+    const double* B;
+    const int* dims;
+    DimExpr a;   // chi_psi (rows)
+    int Dl, e, d, Dr, ny;  // ny = chi_v (right bond of v)
+    int x_type, y_type;
+};
+struct RightMpoDesc {  // Y[b][x][t][c] = sum_{q,b'} B[b][t][q][b'] * X[x][q][c][b']
+    const void* X;
+    void* Y;
+    const double* B;
+    const int* dims;
+    DimExpr c;   // chi_psi (right)
+    int Dl, e, d, Dr, nx;  // nx = chi_v (left bond of v)
+    int x_type, y_type;
+};
+
+// One-sided Jacobi on nvec vectors of length len (row-major X), producing the
+// orthonormal leading vectors Q (r x len), descending singular values, the
+// kept rank (written to dims[rank_idx]) and the discarded weight.
+struct JacobiDesc {
+    double* X;           // nvec x len, overwritten by the rotated vectors
+    double* Q;           // r x len output (may alias nothing else)
+    double* sigma;       // nvec output, descending
+    int* perm;           // nvec scratch
+    const int* dims_in;  // dims used to evaluate nvec/len
+    int* dims_out;       // rank written to dims_out[rank_idx] (may equal dims_in)
+    DimExpr nvec, len;
+    int rank_idx;
+    int max_rank;        // max_bond (and allocation cap)
+    double tol;
+    int mode;            // truncation rule
+    double* log_delta;   // discarded weight of this step (nullable)
+    int* log_rank;       // kept rank of this step (nullable)
+    double* log_spec;    // 32 leading singular values (nullable)
+    double* log_norm2;   // sum of kept s_j^2 (nullable)
+    int* status;         // set to nonzero on non-finite input (nullable)
+    int* conv;           // blocked path: set to 1 when a rotation was applied (nullable)
+};
+
+}  // namespace smps
+
+// ---- host-side launch helpers (defined in the kernel translation units) ----
+namespace smps {
+hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec);
+hipError_t launch_left_mpo(const LeftMpoDesc& d, int a_cap, hipStream_t s);
+hipError_t launch_right_mpo(const RightMpoDesc& d, int c_cap, hipStream_t s);
+// Exact factorization.  Chooses the LDS-resident kernel when nvec_cap*len_cap
+// fits, otherwise the blocked multi-workgroup path (which needs `work`:
+// at least jacobi_work_doubles(nvec_cap, len_cap) doubles).
+hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags,
+                         hipStream_t s);
+size_t jacobi_work_doubles(int nvec_cap, int len_cap);
+hipError_t jacobi_init(int device);
+int jacobi_lds_limit();
+bool jacobi_fits_lds(int nvec_cap, int len_cap);
+hipError_t launch_copy(const double* src, double* dst, const int* dims, DimExpr a, DimExpr b, int cap,
+                       hipStream_t s);
+hipError_t launch_fill(double* dst, double value, size_t n, hipStream_t s);
+hipError_t launch_fill_typed(void* dst, int type, double value, size_t n, hipStream_t s);
+hipError_t launch_copy_int(int* dims, int from, int to, hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+hipError_t launch_set_dims(int* dims, const int* host_vals, int n, hipStream_t s);
+hipError_t launch_sumsq(const double* x, const int* dims, DimExpr n, int n_cap, double* out, hipStream_t s);
+hipError_t launch_check_finite(const double* x, const int* dims, DimExpr n, int n_cap, int* status,
+                               hipStream_t s);
+hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipStream_t s);
+}  // namespace smps

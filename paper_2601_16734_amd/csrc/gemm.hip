@@ -1,0 +1,256 @@
+// Dense contractions on the CDNA4 matrix cores.
+//
+// Every contraction of the sweep (environment growth, the two-site tensor, the
+// environment update, the scalar-product transfer step) is a product of two
+// compact row-major matrices once the tensor indices are grouped, so one
+// tiled MFMA kernel serves them all.  Dimensions may be device-resident
+// (bond ranks chosen by truncation), so the launch grid is sized for the
+// allocation cap and tiles outside the live extent exit at once.
+//
+// Precisions: FP64 (v_mfma_f64_16x16x4, FP64 accumulation), FP32
+// (v_mfma_f32_16x16x4_f32), BF16 (v_mfma_f32_16x16x32_bf16) and split BF16x3
+// (x = hi + lo, product hi*hi + hi*lo + lo*hi, all with FP32 accumulation).
+// Operands are converted from their storage type while being staged in LDS.
+//
+// Workgroup: 256 threads = 4 wave64s arranged 2 x 2, tile 64 x 64, each wave
+// owning a 32 x 32 block of 2 x 2 MFMA 16 x 16 outputs.
+
+#include "common.h"
+
+namespace smps {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64, BN = 64;
+
+template <typename T>
+__device__ __forceinline__ double ldg(const void* p, size_t i) {
+    return (double)((const T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ float ldgf(const void* p, size_t i) {
+    return (float)((const T*)p)[i];
+}
+
+__device__ __forceinline__ unsigned short f2bf(float x) {
+    // round to nearest even (inputs are finite)
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// Element (row r, col c) of the logical M x K operand A, or of the logical K x N operand B.
+template <typename T>
+__device__ __forceinline__ double opA(const void* A, int ta, int M, int K, int r, int k) {
+    return ta ? ldg<T>(A, (size_t)k * M + r) : ldg<T>(A, (size_t)r * K + k);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32 path: BK = 16, LDS holds A as [k][m] and B as [k][n].
+// ---------------------------------------------------------------------------
+template <int PREC, typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g) {
+    using CT = typename std::conditional<PREC == P_F64, double, float>::type;
+    constexpr int BK = 16;
+    const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (m0 >= M || n0 >= N) return;
+    const void* A = (const char*)g.A + (size_t)blockIdx.z * g.sA * sizeof(TA);
+    const void* B = (const char*)g.B + (size_t)blockIdx.z * g.sB * sizeof(TB);
+    void* C = (char*)g.C + (size_t)blockIdx.z * g.sC * sizeof(TC);
+
+    __shared__ CT As[BK][BM + 4];
+    __shared__ CT Bs[BK][BN + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+
+    typedef typename std::conditional<PREC == P_F64, v4d, v4f>::type acc_t;
+    acc_t acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int e0 = 0; e0 < BM * BK; e0 += 256) {
+            const int e = e0 + tid;
+            int mm, kk;
+            if (!g.ta) { mm = e >> 4; kk = e & 15; } else { kk = e >> 6; mm = e & 63; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            CT v = 0;
+            if (gm < M && gk < K) v = (CT)opA<TA>(A, g.ta, M, K, gm, gk);
+            As[kk][mm] = v;
+        }
+#pragma unroll
+        for (int e0 = 0; e0 < BN * BK; e0 += 256) {
+            const int e = e0 + tid;
+            int nn, kk;
+            if (!g.tb) { kk = e >> 6; nn = e & 63; } else { nn = e >> 4; kk = e & 15; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            CT v = 0;
+            if (gn < N && gk < K)
+                v = (CT)(g.tb ? ldg<TB>(B, (size_t)gn * K + gk) : ldg<TB>(B, (size_t)gk * N + gn));
+            Bs[kk][nn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            CT a[2], b[2];
+            for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm + i * 16 + li];
+            for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lk][wn + j * 16 + li];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    if constexpr (PREC == P_F64)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    const CT alpha = (CT)g.alpha;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) {
+                // v_mfma_f64_16x16x4 returns rows lk + 4v; the f32 forms return rows 4lk + v
+                const int row = m0 + wm + i * 16 + (PREC == P_F64 ? lk + 4 * v : lk * 4 + v);
+                const int col = n0 + wn + j * 16 + li;
+                if (row < M && col < N) {
+                    const size_t o = g.tc ? (size_t)col * M + row : (size_t)row * N + col;
+                    ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 / BF16x3 path: BK = 32, LDS holds A as [m][k] and B as [n][k] so that a
+// lane's eight consecutive k values are one 16-byte read.
+// ---------------------------------------------------------------------------
+template <int PREC, typename TA, typename TB, typename TC>
+__global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g) {
+    constexpr int BK = 32, LD = BK + 8;
+    constexpr bool SPLIT = (PREC == P_BF16X3);
+    const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (m0 >= M || n0 >= N) return;
+    const void* A = (const char*)g.A + (size_t)blockIdx.z * g.sA * sizeof(TA);
+    const void* B = (const char*)g.B + (size_t)blockIdx.z * g.sB * sizeof(TB);
+    void* C = (char*)g.C + (size_t)blockIdx.z * g.sC * sizeof(TC);
+
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LD];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LD];
+    __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? BM : 1][LD];
+    __shared__ __attribute__((aligned(16))) unsigned short Bl[SPLIT ? BN : 1][LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+
+    v4f acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.f;
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int e0 = 0; e0 < BM * BK; e0 += 256) {
+            const int e = e0 + tid;
+            int mm, kk;
+            if (!g.ta) { mm = e >> 5; kk = e & 31; } else { kk = e >> 6; mm = e & 63; }
+            const int gm = m0 + mm, gk = k0 + kk;
+            float v = 0.f;
+            if (gm < M && gk < K) v = (float)opA<TA>(A, g.ta, M, K, gm, gk);
+            const unsigned short h = f2bf(v);
+            Ah[mm][kk] = h;
+            if constexpr (SPLIT) Al[mm][kk] = f2bf(v - bf2f(h));
+        }
+#pragma unroll
+        for (int e0 = 0; e0 < BN * BK; e0 += 256) {
+            const int e = e0 + tid;
+            int nn, kk;
+            if (!g.tb) { kk = e >> 6; nn = e & 63; } else { nn = e >> 5; kk = e & 31; }
+            const int gn = n0 + nn, gk = k0 + kk;
+            float v = 0.f;
+            if (gn < N && gk < K)
+                v = (float)(g.tb ? ldg<TB>(B, (size_t)gn * K + gk) : ldg<TB>(B, (size_t)gk * N + gn));
+            const unsigned short h = f2bf(v);
+            Bh[nn][kk] = h;
+            if constexpr (SPLIT) Bl[nn][kk] = f2bf(v - bf2f(h));
+        }
+        __syncthreads();
+        v8bf ah[2], bh[2], al[2], bl[2];
+        for (int i = 0; i < 2; ++i) {
+            ah[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Ah[wm + i * 16 + li][lk * 8]);
+            if constexpr (SPLIT) al[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Al[wm + i * 16 + li][lk * 8]);
+        }
+        for (int j = 0; j < 2; ++j) {
+            bh[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bh[wn + j * 16 + li][lk * 8]);
+            if constexpr (SPLIT) bl[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bl[wn + j * 16 + li][lk * 8]);
+        }
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                if constexpr (SPLIT) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                }
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    const float alpha = (float)g.alpha;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm + i * 16 + lk * 4 + v;
+                const int col = n0 + wn + j * 16 + li;
+                if (row < M && col < N) {
+                    const size_t o = g.tc ? (size_t)col * M + row : (size_t)row * N + col;
+                    ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
+                }
+            }
+}
+
+template <int PREC, typename TA, typename TB, typename TC>
+static void launch_t(const GemmDesc& g, dim3 grid, hipStream_t s) {
+    if constexpr (PREC == P_F64 || PREC == P_F32)
+        hipLaunchKernelGGL((gemm_kernel_f<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel_bf<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g);
+}
+
+template <int PREC>
+static void launch_prec(const GemmDesc& g, dim3 grid, hipStream_t s) {
+    const int code = (g.a_type << 2) | (g.b_type << 1) | g.c_type;
+    switch (code) {
+        case 0: launch_t<PREC, double, double, double>(g, grid, s); break;
+        case 1: launch_t<PREC, double, double, float>(g, grid, s); break;
+        case 2: launch_t<PREC, double, float, double>(g, grid, s); break;
+        case 3: launch_t<PREC, double, float, float>(g, grid, s); break;
+        case 4: launch_t<PREC, float, double, double>(g, grid, s); break;
+        case 5: launch_t<PREC, float, double, float>(g, grid, s); break;
+        case 6: launch_t<PREC, float, float, double>(g, grid, s); break;
+        default: launch_t<PREC, float, float, float>(g, grid, s); break;
+    }
+}
+
+hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec) {
+    if (M_cap <= 0 || N_cap <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid((N_cap + BN - 1) / BN, (M_cap + BM - 1) / BM, batch);
+    switch (prec) {
+        case P_F64: {
+            // the FP64 path keeps every operand in FP64
+            GemmDesc h = g;
+            launch_prec<P_F64>(h, grid, s);
+            break;
+        }
+        case P_F32: launch_prec<P_F32>(g, grid, s); break;
+        case P_BF16X3: launch_prec<P_BF16X3>(g, grid, s); break;
+        default: launch_prec<P_BF16>(g, grid, s); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace smps

@@ -1,0 +1,77 @@
+// Host runtime objects behind the C ABI handles.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+struct smps_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // grow-only workspace arena for apply/simplify/scprod
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    // exact-size cache of device blocks released by destroyed handles
+    std::multimap<size_t, void*> pool;
+    // pinned staging for small read-backs
+    char* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    // diagnostics of the last apply
+    smps_apply_info info{};
+    std::vector<double> log_delta, log_spec, log_norm2;
+    std::vector<int> log_rank;
+    // rank predictor state (device buffers, see mlp.hip)
+    void* mlp = nullptr;
+};
+
+struct smps_mps {
+    smps_ctx* ctx = nullptr;
+    int L = 0;
+    std::vector<int> phys, bonds;
+    int center = -1;
+    double* data = nullptr;
+    size_t bytes = 0;
+    std::vector<size_t> off;  // element offsets
+    size_t site_size(int k) const { return (size_t)bonds[k] * phys[k] * bonds[k + 1]; }
+};
+
+struct smps_mpo {
+    smps_ctx* ctx = nullptr;
+    int L = 0;
+    std::vector<int> pout, pin, bonds;
+    double* data = nullptr;
+    size_t bytes = 0;
+    std::vector<size_t> off;
+    size_t site_size(int k) const { return (size_t)bonds[k] * pout[k] * pin[k] * bonds[k + 1]; }
+};
+
+namespace smps {
+int fail(smps_ctx* c, int code, const std::string& msg);
+void* dev_alloc(smps_ctx* c, size_t bytes);
+void dev_release(smps_ctx* c, void* p, size_t bytes);
+int ensure_arena(smps_ctx* c, size_t bytes);
+int ensure_pinned(smps_ctx* c, size_t bytes);
+smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds);
+
+// Enqueue one apply + compression and collect its results (used by the single
+// and the batched entry points).
+struct ApplyProblem {
+    const smps_mpo* U;
+    const smps_mps* v;
+};
+int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
+              double* trunc_err);
+void mlp_free(smps_ctx* c);
+int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                      const smps_strategy& st, smps_mps** out, double* trunc_err);
+}  // namespace smps
+
+#define SMPS_HIP(c, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t e__ = (expr);                                                                  \
+        if (e__ != hipSuccess)                                                                    \
+            return smps::fail((c), SMPS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+    } while (0)

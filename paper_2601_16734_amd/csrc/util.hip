@@ -1,0 +1,138 @@
+// Small device utilities: copies sized by device-resident dimensions, fills,
+// FP64 sum of squares (the Frobenius norm of a centre tensor) and checks.
+
+#include <cfloat>
+
+#include "common.h"
+
+namespace smps {
+
+__global__ __launch_bounds__(256) void copy_kernel(const double* src, double* dst, const int* dims, DimExpr a,
+                                                  DimExpr b) {
+    const size_t n = (size_t)eval_dim(dims, a) * eval_dim(dims, b);
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+hipError_t launch_copy(const double* src, double* dst, const int* dims, DimExpr a, DimExpr b, int cap,
+                       hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    int blocks = (cap + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, src, dst, dims, a, b);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* dst, double v, size_t n) {
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = v;
+}
+
+hipError_t launch_fill(double* dst, double value, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, value, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_f32_kernel(float* dst, float v, size_t n) {
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = v;
+}
+
+hipError_t launch_fill_typed(void* dst, int type, double value, size_t n, hipStream_t s) {
+    if (type == T_F64) return launch_fill((double*)dst, value, n, s);
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (float*)dst, (float)value, n);
+    return hipGetLastError();
+}
+
+__global__ void copy_int_kernel(int* dims, int from, int to) { dims[to] = dims[from]; }
+
+hipError_t launch_copy_int(int* dims, int from, int to, hipStream_t s) {
+    hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, s, dims, from, to);
+    return hipGetLastError();
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+struct DimsArg {
+    int v[64];
+};
+
+__global__ void set_dims_kernel(int* dims, DimsArg a, int n) {
+    const int i = threadIdx.x;
+    if (i < n) dims[i] = a.v[i];
+}
+
+hipError_t launch_set_dims(int* dims, const int* host_vals, int n, hipStream_t s) {
+    // values travel as kernel arguments (no host buffer has to outlive the call)
+    for (int off = 0; off < n; off += 64) {
+        DimsArg a;
+        const int m = (n - off) < 64 ? (n - off) : 64;
+        for (int i = 0; i < m; ++i) a.v[i] = host_vals[off + i];
+        hipLaunchKernelGGL(set_dims_kernel, dim3(1), dim3(64), 0, s, dims + off, a, m);
+    }
+    return hipGetLastError();
+}
+
+// Sum of squares in FP64: per-thread partials, wavefront shuffles, then LDS.
+__global__ __launch_bounds__(1024) void sumsq_kernel(const double* x, const int* dims, DimExpr nexpr, double* out) {
+    const int n = eval_dim(dims, nexpr);
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) a = fma(x[i], x[i], a);
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    __shared__ double part[16];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += part[w];
+        *out = t;
+    }
+}
+
+hipError_t launch_sumsq(const double* x, const int* dims, DimExpr n, int n_cap, double* out, hipStream_t s) {
+    (void)n_cap;
+    hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(1024), 0, s, x, dims, n, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void check_finite_kernel(const double* x, const int* dims, DimExpr nexpr,
+                                                          int* status) {
+    const int n = eval_dim(dims, nexpr);
+    int bad = 0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) bad |= !isfinite(x[i]);
+    if (bad) atomicOr(status, 1);
+}
+
+hipError_t launch_check_finite(const double* x, const int* dims, DimExpr n, int n_cap, int* status,
+                               hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
+    int blocks = (n_cap + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(check_finite_kernel, dim3(blocks), dim3(256), 0, s, x, dims, n, status);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(const float* src, double* dst, size_t n) {
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = (double)src[i];
+}
+
+hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace smps

@@ -22,9 +22,12 @@ def gpu_available() -> bool:
 
 
 @pytest.fixture(scope="session")
-def lib():
-    """The HIP library binding; GPU tests fail loudly if it is missing."""
+def ctx():
+    """A library context on cuda:0 bound to torch's current stream.  GPU tests
+    fail loudly (no fallback) when the HIP library is missing."""
     if not gpu_available():
         pytest.skip("no GPU visible")
     from paper_2601_16734_amd import binding
-    return binding.load()
+    c = binding.Context(0)
+    yield c
+    c.close()
