@@ -91,6 +91,8 @@ typedef struct {
     int steps;            /* two-site updates performed (site-updates) */
     int rsvd_accepted;    /* randomized factorizations accepted */
     int rsvd_fallbacks;   /* randomized factorizations replaced by the exact SVD */
+    int jacobi_sweeps;    /* Jacobi sweeps summed over the exact factorizations of the sweep */
+    int reserved;
 } smps_apply_info;
 
 /* ---- context ---------------------------------------------------------------

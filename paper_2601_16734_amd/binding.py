@@ -42,7 +42,8 @@ class Strategy(ctypes.Structure):
 
 class ApplyInfo(ctypes.Structure):
     _fields_ = [("error_bound", c_double), ("discarded", c_double), ("norm", c_double), ("sweeps_done", c_int),
-                ("steps", c_int), ("rsvd_accepted", c_int), ("rsvd_fallbacks", c_int)]
+                ("steps", c_int), ("rsvd_accepted", c_int), ("rsvd_fallbacks", c_int), ("jacobi_sweeps", c_int),
+                ("reserved", c_int)]
 
 
 class SmpsError(RuntimeError):

@@ -84,8 +84,10 @@ struct JacobiDesc {
     int* log_rank;       // kept rank of this step (nullable)
     double* log_spec;    // 32 leading singular values (nullable)
     double* log_norm2;   // sum of kept s_j^2 (nullable)
+    int* log_sweeps;     // Jacobi sweeps that rotated (nullable)
     int* status;         // set to nonzero on non-finite input (nullable)
     int* conv;           // blocked path: set to 1 when a rotation was applied (nullable)
+    double* fro2;        // blocked path: ||X||_F^2 (device scalar, filled by the launcher)
 };
 
 }  // namespace smps

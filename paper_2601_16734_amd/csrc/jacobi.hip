@@ -33,52 +33,134 @@ constexpr int SEL_MAX = 2048;          // vectors handled by the select kernel
 
 __device__ __forceinline__ int tourney(int pos, int rd, int n2) {
     // player at position pos in round rd of a round-robin over n2 (even) players
-    return pos == 0 ? 0 : ((pos - 1 + rd) % (n2 - 1)) + 1;
+    if (pos == 0) return 0;
+    int x = pos - 1 + rd;  // < 2 (n2 - 1)
+    if (x >= n2 - 1) x -= n2 - 1;
+    return x + 1;
 }
 
-// Orthogonalise nv vectors (row j at W + j*ld, length len) held in LDS.
-// Returns (block-uniform) whether any rotation was applied.
-__device__ bool jacobi_orthogonalize(double* W, int nv, int len, int ld, int* s_flag) {
+// Numerical rank floor: a vector whose norm is at most
+// eps * max(nvec, len) * ||X||_F is rounding noise of a rank-deficient matrix;
+// it takes part in no rotation and counts as a zero singular value.
+__device__ __forceinline__ double zero_floor2(double total2, int nv, int len) {
+    const double f = DBL_EPSILON * (double)(nv > len ? nv : len);
+    return f * f * total2;
+}
+
+// Cross-lane move inside a row of 16 lanes (DPP), for a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a row; every lane ends with the identical value
+// (each step adds a disjoint partner, and addition is commutative).
+__device__ __forceinline__ double row_sum16(double x) {
+    x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]: partner lane ^ 1
+    x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]: partner lane ^ 2
+    x += dpp_mov<0x141>(x);  // row_half_mirror: quad 0 <-> quad 1, quad 2 <-> quad 3
+    x += dpp_mov<0x140>(x);  // row_mirror: lanes 0-7 <-> lanes 8-15
+    return x;
+}
+
+// Orthogonalise nv vectors (row j at W + j*ld, length len) held in LDS; nrm
+// (nv doubles of LDS) holds their squared norms, recomputed exactly at the
+// start of every sweep and updated in between by the exact 2x2 relations
+// (a' = a - t c, b' = b + t c), so a pair needs one dot product only.
+// A group of 16 lanes (one DPP row) handles a pair; the pairs of a round of
+// the round-robin tournament are disjoint and run concurrently.
+// E > 0: each lane keeps its E elements of both vectors in registers between
+// the dot product and the rotation (len <= 16 E); E = 0: generic strided loop.
+// Returns (block-uniform) the number of sweeps that applied a rotation.
+template <int E>
+__device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double total2,
+                             int true_len) {
     const int tid = threadIdx.x;
-    if (nv < 2) return false;
-    const double tol = 2.0 * DBL_EPSILON * sqrt((double)len);
-    const double tiny = DBL_MIN * 1.0e4;
+    if (nv < 2) return 0;
+    // cosine threshold: rounding in a length-n dot product is ~eps*sqrt(n); eps*n leaves margin
+    const double tol = DBL_EPSILON * (double)(true_len > 16 ? true_len : 16);
+    const double tiny = fmax(DBL_MIN * 1.0e4, zero_floor2(total2, nv, true_len));
     const int P = (nv + 1) / 2, n2 = 2 * P;
-    int g = 64;
-    while (g > 1 && g * P > JT) g >>= 1;
+    constexpr int g = 16;
     const int gl = tid & (g - 1), gi = tid / g, ngroups = JT / g;
-    bool any = false;
+    int any = 0;
     for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+        for (int j = gi; j < nv; j += ngroups) {
+            const double* w = W + j * ld;
+            double a0 = 0.0, a1 = 0.0;
+            int i = gl;
+            for (; i + g < len; i += 2 * g) {
+                a0 = fma(w[i], w[i], a0);
+                a1 = fma(w[i + g], w[i + g], a1);
+            }
+            if (i < len) a0 = fma(w[i], w[i], a0);
+            const double a = row_sum16(a0 + a1);
+            if (gl == 0) nrm[j] = a;
+        }
         if (tid == 0) *s_flag = 0;
         __syncthreads();
         for (int rd = 0; rd < n2 - 1; ++rd) {
             for (int pi = gi; pi < P; pi += ngroups) {
                 const int p = tourney(pi, rd, n2), q = tourney(n2 - 1 - pi, rd, n2);
                 if (p >= nv || q >= nv) continue;
-                double* wp = W + (size_t)p * ld;
-                double* wq = W + (size_t)q * ld;
-                double a = 0.0, b = 0.0, c = 0.0;
-                for (int i = gl; i < len; i += g) {
-                    const double x = wp[i], y = wq[i];
-                    a = fma(x, x, a);
-                    b = fma(y, y, b);
-                    c = fma(x, y, c);
+                const double a = nrm[p], b = nrm[q];
+                if (!(a > tiny && b > tiny)) continue;  // uniform in the group
+                double* wp = W + p * ld;
+                double* wq = W + q * ld;
+                double x[E > 0 ? E : 1], y[E > 0 ? E : 1];
+                double c;
+                if constexpr (E > 0) {
+                    double cc[2] = {0.0, 0.0};
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int i = gl + g * e;  // len == 16 E here (zero padded)
+                        x[e] = wp[i];
+                        y[e] = wq[i];
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e) cc[e & 1] = fma(x[e], y[e], cc[e & 1]);
+                    c = row_sum16(cc[0] + cc[1]);
+                } else {
+                    double c0 = 0.0, c1 = 0.0;
+                    int i = gl;
+                    for (; i + g < len; i += 2 * g) {
+                        c0 = fma(wp[i], wq[i], c0);
+                        c1 = fma(wp[i + g], wq[i + g], c1);
+                    }
+                    if (i < len) c0 = fma(wp[i], wq[i], c0);
+                    c = row_sum16(c0 + c1);
                 }
-                for (int off = g >> 1; off > 0; off >>= 1) {
-                    a += __shfl_xor(a, off, g);
-                    b += __shfl_xor(b, off, g);
-                    c += __shfl_xor(c, off, g);
-                }
-                if (a > tiny && b > tiny && fabs(c) > tol * sqrt(a) * sqrt(b)) {
+                if (fabs(c) > tol * sqrt(a * b)) {
+                    // Rutishauser's rotation: t = sgn(z) / (|z| + sqrt(1 + z^2)), z = (b - a) / 2c;
+                    // c^2 + s^2 = 1 is what keeps the transformation orthogonal, so
+                    // cs = 1/sqrt(1 + t^2) gets a Newton step after the hardware rsqrt.
                     const double zeta = (b - a) / (2.0 * c);
                     const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                    for (int i = gl; i < len; i += g) {
-                        const double x = wp[i], y = wq[i];
-                        wp[i] = cs * x - sn * y;
-                        wq[i] = sn * x + cs * y;
+                    const double h = 1.0 + t * t;
+                    double cs = __builtin_amdgcn_rsq(h);
+                    cs = cs * fma(-0.5 * h * cs, cs, 1.5);
+                    const double sn = cs * t;
+                    if constexpr (E > 0) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const int i = gl + g * e;
+                            wp[i] = cs * x[e] - sn * y[e];
+                            wq[i] = sn * x[e] + cs * y[e];
+                        }
+                    } else {
+                        for (int i = gl; i < len; i += g) {
+                            const double xv = wp[i], yv = wq[i];
+                            wp[i] = cs * xv - sn * yv;
+                            wq[i] = sn * xv + cs * yv;
+                        }
                     }
-                    if (gl == 0) *s_flag = 1;
+                    if (gl == 0) {
+                        nrm[p] = fmax(a - t * c, 0.0);
+                        nrm[q] = b + t * c;
+                        *s_flag = 1;
+                    }
                 }
             }
             __syncthreads();
@@ -86,9 +168,19 @@ __device__ bool jacobi_orthogonalize(double* W, int nv, int len, int ld, int* s_
         const int rot = *s_flag;
         __syncthreads();
         if (!rot) break;
-        any = true;
+        ++any;
     }
     return any;
+}
+
+// register-held elements per lane for a vector length cap (0: strided loop)
+static int elems_for(int len_cap) {
+    if (len_cap <= 16) return 1;
+    if (len_cap <= 32) return 2;
+    if (len_cap <= 64) return 4;
+    if (len_cap <= 128) return 8;
+    if (len_cap <= 256) return 16;
+    return 0;
 }
 
 // Norms, order, rank rule and discarded weight for nv vectors; results in
@@ -103,9 +195,19 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
         const double* w = W + (size_t)j * ld;
         double a = 0.0;
         for (int i = gl; i < len; i += g) a = fma(w[i], w[i], a);
-        for (int off = g >> 1; off > 0; off >>= 1) a += __shfl_xor(a, off, g);
-        if (gl == 0) sig_raw[j] = sqrt(a);
+        a = row_sum16(a);
+        if (gl == 0) sig_raw[j] = a;
     }
+    __syncthreads();
+    // squared norms -> singular values, with the numerical rank floor
+    __shared__ double s_floor2;
+    if (tid == 0) {
+        double t2 = 0.0;
+        for (int j = 0; j < nv; ++j) t2 += sig_raw[j];
+        s_floor2 = zero_floor2(t2, nv, len);
+    }
+    __syncthreads();
+    for (int j = tid; j < nv; j += JT) sig_raw[j] = sig_raw[j] > s_floor2 ? sqrt(sig_raw[j]) : 0.0;
     __syncthreads();
     // descending order with ties broken by index
     for (int j = tid; j < nv; j += JT) {
@@ -189,41 +291,69 @@ __device__ void jacobi_write_rows(const double* W, int len, int ld, const double
     }
 }
 
+template <int E>
 __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d) {
     extern __shared__ double sm[];
     __shared__ int s_flag, s_bad;
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
+    // rows padded with zeros to 16 E so the register path needs no bounds tests
+    const int ld = E > 0 ? 16 * E : len;
     const int tid = threadIdx.x;
     double* W = sm;
-    double* sig_raw = sm + (size_t)nv * len;
+    double* sig_raw = sm + (size_t)nv * ld;
     double* sig_sorted = sig_raw + nv;
     int* perm = (int*)(sig_sorted + nv);
     if (tid == 0) s_bad = 0;
     __syncthreads();
     int bad = 0;
-    for (size_t i = tid; i < (size_t)nv * len; i += JT) {
-        const double x = d.X[i];
-        bad |= !isfinite(x);
-        W[i] = x;
+    for (int e = tid; e < nv * ld; e += JT) {
+        const int j = e / ld, i = e - j * ld;
+        double x = 0.0;
+        if (i < len) {
+            x = d.X[(size_t)j * len + i];
+            bad |= !isfinite(x);
+        }
+        W[e] = x;
     }
     if (bad) s_bad = 1;
     __syncthreads();
     if (s_bad) {
-        for (size_t i = tid; i < (size_t)nv * len; i += JT) W[i] = 0.0;
+        for (int e = tid; e < nv * ld; e += JT) W[e] = 0.0;
         if (tid == 0 && d.status) *d.status = 1;
         __syncthreads();
     }
-    jacobi_orthogonalize(W, nv, len, len, &s_flag);
-    const int r = jacobi_select(W, nv, len, len, sig_raw, sig_sorted, perm, d, &s_delta);
-    jacobi_write_rows(W, len, len, sig_sorted, perm, r, d.Q);
+    // ||X||_F^2 (summed in vector order, deterministic) for the rank floor
+    __shared__ double s_total2;
+    {
+        const int gl = tid & 15, gi = tid >> 4;
+        for (int j = gi; j < nv; j += JT / 16) {
+            double a = 0.0;
+            for (int i = gl; i < len; i += 16) a = fma(W[j * ld + i], W[j * ld + i], a);
+            a = row_sum16(a);
+            if (gl == 0) sig_raw[j] = a;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double t2 = 0.0;
+            for (int j = 0; j < nv; ++j) t2 += sig_raw[j];
+            s_total2 = t2;
+        }
+        __syncthreads();
+    }
+    const int nsw = jacobi_orth_t<E>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag, s_total2, len);
+    if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
+    const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
+    jacobi_write_rows(W, len, ld, sig_sorted, perm, r, d.Q);
 }
 
 // One round of the blocked path: workgroup i takes the block pair of
 // tournament position i, orthogonalises the union in LDS, writes it back.
+template <int E>
 __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d, int bs, int nblk2, int rd) {
     extern __shared__ double sm[];
     __shared__ int s_flag, s_bad;
+    __shared__ double s_nrm[64];
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     const int bp = tourney(blockIdx.x, rd, nblk2), bq = tourney(nblk2 - 1 - blockIdx.x, rd, nblk2);
     // vectors of the two blocks that exist
@@ -251,7 +381,7 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d, int bs, 
         if (tid == 0 && d.status) *d.status = 1;
         return;
     }
-    const bool any = jacobi_orthogonalize(sm, nloc, len, len, &s_flag);
+    const bool any = jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, *d.fro2, len) > 0;
     if (!any) return;
     for (size_t e = tid; e < (size_t)nloc * len; e += JT) {
         const int j = (int)(e / len), l = (int)(e % len);
@@ -285,6 +415,26 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d) {
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
+// ||X||_F^2 for the blocked path's rank floor: per-vector sums in vector order.
+__global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d) {
+    __shared__ double part[SEL_MAX];
+    const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
+    const int tid = threadIdx.x, gl = tid & 15, gi = tid >> 4;
+    for (int j = gi; j < nv; j += JT / 16) {
+        const double* w = d.X + (size_t)j * len;
+        double a = 0.0;
+        for (int i = gl; i < len; i += 16) a = fma(w[i], w[i], a);
+        a = row_sum16(a);
+        if (gl == 0) part[j] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int j = 0; j < nv; ++j) t += part[j];
+        *d.fro2 = t;
+    }
+}
+
 // LDS a Jacobi workgroup may use: the device limit, capped at 160 KB.
 static int g_lds_bytes = 64 * 1024;
 
@@ -295,13 +445,19 @@ hipError_t jacobi_init(int device) {
     lim = lim < LDS_BYTES ? lim : LDS_BYTES;
     // the dynamic part may use what the kernels' static LDS leaves free
     size_t stat = 0;
-    for (const void* f : {(const void*)jacobi_lds_kernel, (const void*)jacobi_panel_kernel}) {
+    const void* kernels[] = {(const void*)jacobi_lds_kernel<0>,   (const void*)jacobi_lds_kernel<1>,
+                             (const void*)jacobi_lds_kernel<2>,   (const void*)jacobi_lds_kernel<4>,
+                             (const void*)jacobi_lds_kernel<8>,   (const void*)jacobi_lds_kernel<16>,
+                             (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
+                             (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
+                             (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>};
+    for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
     }
     int dyn = lim - (int)((stat + 255) / 256 * 256);
     bool ok = true;
-    for (const void* f : {(const void*)jacobi_lds_kernel, (const void*)jacobi_panel_kernel})
+    for (const void* f : kernels)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();  // keep the default limit
@@ -314,7 +470,9 @@ hipError_t jacobi_init(int device) {
 int jacobi_lds_limit() { return g_lds_bytes; }
 
 static size_t lds_need(int nvec, int len) {
-    return sizeof(double) * ((size_t)nvec * len + 2 * (size_t)nvec) + sizeof(int) * (size_t)nvec + 64;
+    const int e = elems_for(len);
+    const size_t ld = e > 0 ? 16 * (size_t)e : (size_t)len;
+    return sizeof(double) * ((size_t)nvec * ld + 2 * (size_t)nvec) + sizeof(int) * (size_t)nvec + 64;
 }
 
 bool jacobi_fits_lds(int nvec_cap, int len_cap) { return lds_need(nvec_cap, len_cap) <= (size_t)g_lds_bytes - 1024; }
@@ -332,7 +490,15 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     (void)work;
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
     if (jacobi_fits_lds(nvec_cap, len_cap)) {
-        hipLaunchKernelGGL(jacobi_lds_kernel, dim3(1), dim3(JT), lds_need(nvec_cap, len_cap), s, d);
+        const size_t shm = lds_need(nvec_cap, len_cap);
+        switch (elems_for(len_cap)) {
+            case 1: hipLaunchKernelGGL(jacobi_lds_kernel<1>, dim3(1), dim3(JT), shm, s, d); break;
+            case 2: hipLaunchKernelGGL(jacobi_lds_kernel<2>, dim3(1), dim3(JT), shm, s, d); break;
+            case 4: hipLaunchKernelGGL(jacobi_lds_kernel<4>, dim3(1), dim3(JT), shm, s, d); break;
+            case 8: hipLaunchKernelGGL(jacobi_lds_kernel<8>, dim3(1), dim3(JT), shm, s, d); break;
+            case 16: hipLaunchKernelGGL(jacobi_lds_kernel<16>, dim3(1), dim3(JT), shm, s, d); break;
+            default: hipLaunchKernelGGL(jacobi_lds_kernel<0>, dim3(1), dim3(JT), shm, s, d); break;
+        }
         return hipGetLastError();
     }
     if (nvec_cap > SEL_MAX) return hipErrorInvalidValue;
@@ -341,12 +507,22 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     int nblk = (nvec_cap + bs - 1) / bs;
     if (nblk & 1) ++nblk;
     const size_t shm = sizeof(double) * 2 * (size_t)bs * len_cap;
+    const int E = elems_for(len_cap);
     JacobiDesc dd = d;
     dd.conv = flags;
+    if (!dd.fro2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd);
     for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
         hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
         for (int rd = 0; rd < nblk - 1; ++rd)
-            hipLaunchKernelGGL(jacobi_panel_kernel, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd);
+            switch (E) {
+                case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+                case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+                case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+                case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+                case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+                default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
+            }
         int h = 0;
         hipError_t e = hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;

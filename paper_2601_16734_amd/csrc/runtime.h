@@ -22,7 +22,7 @@ struct smps_ctx {
     // diagnostics of the last apply
     smps_apply_info info{};
     std::vector<double> log_delta, log_spec, log_norm2;
-    std::vector<int> log_rank;
+    std::vector<int> log_rank, log_sweeps;
     // rank predictor state (device buffers, see mlp.hip)
     void* mlp = nullptr;
 };

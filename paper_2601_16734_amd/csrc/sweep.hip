@@ -53,10 +53,10 @@ struct Plan {
     size_t es = 8;      // its size
     std::vector<int> e, dv, Dm, chiv, capb;
     // offsets into the workspace
-    size_t o_dims, o_status, o_flag, o_norm2;
+    size_t o_dims, o_status, o_flag, o_norm2, o_fro2;
     std::vector<size_t> o_psi, o_L, o_R, o_XL, o_XR;
     size_t o_tmp, o_theta, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
-    size_t o_ldelta, o_lrank, o_lspec, o_lnorm2;
+    size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
     size_t o_R64a, o_R64b, o_XR64, o_Y64;
     int steps = 0;
     size_t max_theta = 0, max_tmp = 0, max_env = 0, max_xr = 0;
@@ -99,6 +99,7 @@ static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const sm
     p.o_status = lay.add(sizeof(int));
     p.o_flag = lay.add(sizeof(int));
     p.o_norm2 = lay.add(sizeof(double));
+    p.o_fro2 = lay.add(sizeof(double));
     p.o_psi.resize(L);
     p.o_L.resize(L + 1);
     p.o_R.resize(L + 1);
@@ -145,6 +146,7 @@ static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const sm
     p.o_lrank = lay.add(4 * (size_t)std::max(1, p.steps));
     p.o_lspec = lay.add(8 * 32 * (size_t)std::max(1, p.steps));
     p.o_lnorm2 = lay.add(8 * (size_t)std::max(1, p.steps));
+    p.o_lsweeps = lay.add(4 * (size_t)std::max(1, p.steps));
     if (p.et != T_F64) {
         p.o_R64a = lay.add(8 * p.max_env);
         p.o_R64b = lay.add(8 * p.max_env);
@@ -260,11 +262,13 @@ struct Enq {
         d.tol = tol;
         d.mode = mode;
         d.status = at<int>(p.o_status);
+        d.fro2 = at<double>(p.o_fro2);
         if (step >= 0) {
             d.log_delta = at<double>(p.o_ldelta) + step;
             d.log_rank = at<int>(p.o_lrank) + step;
             d.log_spec = at<double>(p.o_lspec) + 32 * (size_t)step;
             d.log_norm2 = at<double>(p.o_lnorm2) + step;
+            d.log_sweeps = at<int>(p.o_lsweeps) + step;
         }
         return d;
     }
@@ -385,6 +389,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     c->log_rank.assign(steps, 0);
     c->log_spec.assign((size_t)steps * 32, 0.0);
     c->log_norm2.assign(steps, 0.0);
+    c->log_sweeps.assign(steps, 0);
     SMPS_HIP(c, hipMemcpyAsync(hd.data(), q.dims, sizeof(int) * (L + 2), hipMemcpyDeviceToHost, q.s));
     SMPS_HIP(c, hipMemcpyAsync(&status, q.at(p.o_status), sizeof(int), hipMemcpyDeviceToHost, q.s));
     SMPS_HIP(c, hipMemcpyAsync(&norm2, q.at(p.o_norm2), sizeof(double), hipMemcpyDeviceToHost, q.s));
@@ -394,6 +399,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
         SMPS_HIP(c, hipMemcpyAsync(c->log_spec.data(), q.at(p.o_lspec), 8 * 32 * (size_t)steps,
                                    hipMemcpyDeviceToHost, q.s));
         SMPS_HIP(c, hipMemcpyAsync(c->log_norm2.data(), q.at(p.o_lnorm2), 8 * steps, hipMemcpyDeviceToHost, q.s));
+        SMPS_HIP(c, hipMemcpyAsync(c->log_sweeps.data(), q.at(p.o_lsweeps), 4 * steps, hipMemcpyDeviceToHost, q.s));
     }
     SMPS_HIP(c, hipStreamSynchronize(q.s));
     if (status) return fail(c, SMPS_ENUMERIC, "non-finite values in a two-site tensor or the result");
@@ -417,6 +423,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     c->info.norm = std::sqrt(norm2);
     c->info.sweeps_done = st.max_sweeps;
     c->info.steps = steps;
+    for (int i = 0; i < steps; ++i) c->info.jacobi_sweeps += c->log_sweeps[i];
     if (trunc_err) *trunc_err = eb;
     *out = m;
     return SMPS_OK;

@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
     # smps_strategy: int, double, int, int, double, int, int
     assert ctypes.sizeof(binding.Strategy) == 40
     assert binding.Strategy.tol.offset == 8 and binding.Strategy.sweep_tol.offset == 24
-    assert ctypes.sizeof(binding.ApplyInfo) == 40
+    assert ctypes.sizeof(binding.ApplyInfo) == 48
 
 
 def test_missing_library_fails_loudly(tmp_path):
