@@ -104,6 +104,12 @@ int smps_ctx_destroy(smps_ctx *ctx);
 const char *smps_last_error(const smps_ctx *ctx);
 /* Bytes of device workspace the context currently holds (grow-only arena). */
 int smps_ctx_workspace_bytes(const smps_ctx *ctx, size_t *bytes);
+/* Kernel timing with HIP events recorded on the context stream around every
+   launch of a category (0 = factorization, 1 = contractions).  on != 0 enables
+   it and clears the counters; smps_ctx_kernel_time returns the accumulated
+   milliseconds and the number of timed launches of a category since then. */
+int smps_ctx_set_profiling(smps_ctx *ctx, int on);
+int smps_ctx_kernel_time(smps_ctx *ctx, int category, double *total_ms, long long *launches);
 
 /* ---- MPS (Sec. 2.1, Eq. general-MPS) ---------------------------------------
  * L >= 1 sites; phys[L] local dimensions; bonds[L+1] with bonds[0] =

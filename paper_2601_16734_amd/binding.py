@@ -26,7 +26,8 @@ MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
 
 # every symbol the header declares, in declaration order
 EXPORTS = [
-    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes",
+    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes", "smps_ctx_set_profiling",
+    "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
     "smps_last_info", "smps_last_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
@@ -70,6 +71,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_ctx_destroy": (c_int, [vp]),
         "smps_last_error": (ctypes.c_char_p, [vp]),
         "smps_ctx_workspace_bytes": (c_int, [vp, POINTER(c_size_t)]),
+        "smps_ctx_set_profiling": (c_int, [vp, c_int]),
+        "smps_ctx_kernel_time": (c_int, [vp, c_int, POINTER(c_double), POINTER(ctypes.c_longlong)]),
         "smps_mps_create": (c_int, [vp, c_int, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
         "smps_mps_create_device": (c_int, [vp, c_int, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
         "smps_mps_destroy": (c_int, [vp]),
@@ -287,6 +290,17 @@ class Context:
                                            ranks.ctypes.data_as(POINTER(c_int)),
                                            spec.ctypes.data_as(POINTER(c_double)), byref(n)))
         return deltas, ranks, spec
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.smps_ctx_set_profiling(self.h, 1 if on else 0))
+
+    def kernel_time(self, category: int = 0):
+        """(total milliseconds, launches) of timed launches of a category
+        (0 = factorization, 1 = contractions) since profiling was enabled."""
+        ms = c_double()
+        n = ctypes.c_longlong()
+        self._check(self.lib.smps_ctx_kernel_time(self.h, int(category), byref(ms), byref(n)))
+        return ms.value, n.value
 
     def workspace_bytes(self) -> int:
         b = c_size_t()

@@ -57,6 +57,39 @@ int ensure_pinned(smps_ctx* c, size_t bytes) {
     return SMPS_OK;
 }
 
+int prof_begin(smps_ctx* c, hipStream_t s) {
+    if (!c->profiling) return -1;
+    while ((int)c->ev_pool.size() < c->ev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        c->ev_pool.push_back(e);
+    }
+    const int tok = c->ev_used;
+    c->ev_used += 2;
+    if (hipEventRecord(c->ev_pool[tok], s) != hipSuccess) return -1;
+    return tok;
+}
+
+void prof_end(smps_ctx* c, hipStream_t s, int token, int category) {
+    if (token < 0) return;
+    if (hipEventRecord(c->ev_pool[token + 1], s) != hipSuccess) return;
+    c->ev_pending[category & 1].emplace_back(token, token + 1);
+}
+
+void prof_collect(smps_ctx* c) {
+    for (int cat = 0; cat < 2; ++cat) {
+        for (auto& pr : c->ev_pending[cat]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]) == hipSuccess) {
+                c->prof_ms[cat] += ms;
+                c->prof_n[cat] += 1;
+            }
+        }
+        c->ev_pending[cat].clear();
+    }
+    c->ev_used = 0;
+}
+
 smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds) {
     smps_mps* m = new smps_mps();
     m->ctx = c;
@@ -130,12 +163,34 @@ int smps_ctx_destroy(smps_ctx* c) {
     if (c->arena) hipFree(c->arena);
     if (c->pinned) hipHostFree(c->pinned);
     for (auto& kv : c->pool) hipFree(kv.second);
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     mlp_free(c);
     delete c;
     return SMPS_OK;
 }
 
 const char* smps_last_error(const smps_ctx* c) { return c ? c->err.c_str() : "context is NULL"; }
+
+int smps_ctx_set_profiling(smps_ctx* c, int on) {
+    if (!c) return SMPS_EINVAL;
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    c->profiling = on != 0;
+    for (int cat = 0; cat < 2; ++cat) {
+        c->prof_ms[cat] = 0.0;
+        c->prof_n[cat] = 0;
+    }
+    return SMPS_OK;
+}
+
+int smps_ctx_kernel_time(smps_ctx* c, int category, double* total_ms, long long* launches) {
+    if (!c || category < 0 || category > 1) return SMPS_EINVAL;
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    prof_collect(c);
+    if (total_ms) *total_ms = c->prof_ms[category];
+    if (launches) *launches = c->prof_n[category];
+    return SMPS_OK;
+}
 
 int smps_ctx_workspace_bytes(const smps_ctx* c, size_t* bytes) {
     if (!c || !bytes) return SMPS_EINVAL;

@@ -88,6 +88,8 @@ struct JacobiDesc {
     int* status;         // set to nonzero on non-finite input (nullable)
     int* conv;           // blocked path: set to 1 when a rotation was applied (nullable)
     double* fro2;        // blocked path: ||X||_F^2 (device scalar, filled by the launcher)
+    double* basis;       // len x len: all normalised vectors when they span R^len, else the
+                         // identity; pre-rotates the next factorization at this bond (nullable)
 };
 
 }  // namespace smps

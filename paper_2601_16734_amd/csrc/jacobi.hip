@@ -282,12 +282,20 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
 
 // Kept rows: Q[i] = W[perm[i]] / s_i (a zero vector only occurs when the
 // whole matrix is zero and one row is kept: it becomes the first unit vector).
-__device__ void jacobi_write_rows(const double* W, int len, int ld, const double* sig_sorted, const int* perm,
-                                  int r, double* Q) {
+__device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, const double* sig_sorted,
+                                  const int* perm, int r, double* Q, double* basis) {
     for (size_t e = threadIdx.x; e < (size_t)r * len; e += JT) {
         const int i = (int)(e / len), l = (int)(e % len);
         const double s = sig_sorted[i];
         Q[e] = s > 0.0 ? W[(size_t)perm[i] * ld + l] / s : (l == i ? 1.0 : 0.0);
+    }
+    if (!basis) return;
+    // len x len basis for the next visit of this bond: every normalised vector
+    // when they span the whole space, else the identity (no warm start)
+    const bool full = nv >= len && sig_sorted[len - 1] > 0.0;
+    for (size_t e = threadIdx.x; e < (size_t)len * len; e += JT) {
+        const int i = (int)(e / len), l = (int)(e % len);
+        basis[e] = full ? W[(size_t)perm[i] * ld + l] / sig_sorted[i] : (l == i ? 1.0 : 0.0);
     }
 }
 
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d) {
     const int nsw = jacobi_orth_t<E>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag, s_total2, len);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
-    jacobi_write_rows(W, len, ld, sig_sorted, perm, r, d.Q);
+    jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis);
 }
 
 // One round of the blocked path: workgroup i takes the block pair of
@@ -403,14 +411,22 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d) {
 }
 
 __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d) {
-    const int len = eval_dim(d.dims_in, d.len);
+    const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     const int r = d.dims_out[d.rank_idx];
     const int i = blockIdx.y;
-    if (i >= r) return;
-    const double s = d.sigma[i];
-    const double* w = d.X + (size_t)d.perm[i] * len;
-    for (int l = blockIdx.x * 256 + threadIdx.x; l < len; l += gridDim.x * 256)
-        d.Q[(size_t)i * len + l] = s > 0.0 ? w[l] / s : (l == i ? 1.0 : 0.0);
+    if (i < r) {
+        const double s = d.sigma[i];
+        const double* w = d.X + (size_t)d.perm[i] * len;
+        for (int l = blockIdx.x * 256 + threadIdx.x; l < len; l += gridDim.x * 256)
+            d.Q[(size_t)i * len + l] = s > 0.0 ? w[l] / s : (l == i ? 1.0 : 0.0);
+    }
+    if (d.basis && i < len) {
+        const bool full = nv >= len && d.sigma[len - 1] > 0.0;
+        const double s = full ? d.sigma[i] : 0.0;
+        const double* w = d.X + (size_t)(full ? d.perm[i] : 0) * len;
+        for (int l = blockIdx.x * 256 + threadIdx.x; l < len; l += gridDim.x * 256)
+            d.basis[(size_t)i * len + l] = full ? w[l] / s : (l == i ? 1.0 : 0.0);
+    }
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
@@ -531,7 +547,8 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
         if (!h) break;
     }
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd);
-    hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, nvec_cap), dim3(256), 0, s, dd);
+    const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
+    hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows), dim3(256), 0, s, dd);
     return hipGetLastError();
 }
 

@@ -25,6 +25,13 @@ struct smps_ctx {
     std::vector<int> log_rank, log_sweeps;
     // rank predictor state (device buffers, see mlp.hip)
     void* mlp = nullptr;
+    // optional per-category kernel timing (events recorded on the stream)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pending[2];  // (start, stop) indices per category
+    int ev_used = 0;
+    double prof_ms[2] = {0.0, 0.0};
+    long long prof_n[2] = {0, 0};
 };
 
 struct smps_mps {
@@ -54,6 +61,12 @@ void* dev_alloc(smps_ctx* c, size_t bytes);
 void dev_release(smps_ctx* c, void* p, size_t bytes);
 int ensure_arena(smps_ctx* c, size_t bytes);
 int ensure_pinned(smps_ctx* c, size_t bytes);
+// Kernel timing helpers: prof_begin returns a token (or -1 when profiling is
+// off) that prof_end closes; prof_collect folds finished pairs into the totals
+// (call after the stream has been synchronised).
+int prof_begin(smps_ctx* c, hipStream_t s);
+void prof_end(smps_ctx* c, hipStream_t s, int token, int category);
+void prof_collect(smps_ctx* c);
 smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds);
 
 // Enqueue one apply + compression and collect its results (used by the single

@@ -54,8 +54,8 @@ struct Plan {
     std::vector<int> e, dv, Dm, chiv, capb;
     // offsets into the workspace
     size_t o_dims, o_status, o_flag, o_norm2, o_fro2;
-    std::vector<size_t> o_psi, o_L, o_R, o_XL, o_XR;
-    size_t o_tmp, o_theta, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
+    std::vector<size_t> o_psi, o_L, o_R, o_XL, o_XR, o_basis;
+    size_t o_tmp, o_theta, o_theta2, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
     size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
     size_t o_R64a, o_R64b, o_XR64, o_Y64;
     int steps = 0;
@@ -136,6 +136,13 @@ static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const sm
     for (int k = 0; k < L; ++k) p.max_nvec = std::max(p.max_nvec, c[k]);
     p.o_tmp = lay.add(p.es * p.max_tmp);
     p.o_theta = lay.add(8 * p.max_theta);
+    p.o_theta2 = lay.add(8 * p.max_theta);
+    // per bond: the singular basis of the last factorization there (warm start)
+    p.o_basis.assign(std::max(1, L - 1), 0);
+    for (int k = 0; k + 1 < L; ++k) {
+        const size_t nb = std::max((size_t)c[k] * e[k], (size_t)e[k + 1] * c[k + 2]);
+        p.o_basis[k] = lay.add(8 * nb * nb);
+    }
     p.o_Q = lay.add(8 * p.max_theta);
     p.o_carry = lay.add(8 * p.max_theta);
     p.o_tmpB = lay.add(8 * p.max_theta);
@@ -167,6 +174,15 @@ struct Enq {
     hipStream_t s;
     int* dims;
     mutable const char* where = "";
+    smps_ctx* ctx = nullptr;
+
+    // exact factorization, timed as category 0 when profiling is on
+    hipError_t jac_launch(const JacobiDesc& d, int nvec_cap, int len_cap) const {
+        const int tok = ctx ? prof_begin(ctx, s) : -1;
+        hipError_t e = launch_jacobi(d, nvec_cap, len_cap, nullptr, at<int>(p.o_flag), s);
+        if (ctx) prof_end(ctx, s, tok, 0);
+        return e;
+    }
 
     template <typename T = void>
     T* at(size_t off) const { return (T*)(base + off); }
@@ -301,7 +317,7 @@ struct Enq {
             const int lenc = e[k] * c[k + 1];
             CK(launch_copy(at<double>(p.o_psi[k]), theta, dims, ddyn(k), ddyn(k + 1, e[k]), c[k] * lenc, s));
             JacobiDesc d = jac(theta, Q, ddyn(k), ddyn(k + 1, e[k]), RS, c[k], 0.0, SMPS_TRUNC_REL_NORM2, -1);
-            CK(launch_jacobi(d, c[k], lenc, nullptr, at<int>(p.o_flag), s));
+            CK(jac_launch(d, c[k], lenc));
             // carry = psi_k Q^T  (chi_k x r)
             CK(gemm(at(p.o_psi[k]), T_F64, Q, T_F64, at(p.o_carry), T_F64, ddyn(k), ddyn(RS), ddyn(k + 1, e[k]),
                     0, 1, 0, c[k], c[k], P_F64));
@@ -330,9 +346,18 @@ struct Enq {
                         ddyn(k + 2, e[k + 1]), dconst(p.Dm[k + 1] * p.chiv[k + 1]), 0, 0, 1, c[k] * e[k],
                         e[k + 1] * c[k + 2], p.prec));
                 const int mr = std::min(st.max_bond, c[k + 1]);
-                JacobiDesc d = jac(theta, at<double>(p.o_Q), ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), k + 1, mr, st.tol,
+                // warm start: rotate the columns by the right singular basis this bond
+                // produced in the previous right-to-left pass (identity when it was not full)
+                double* X = theta;
+                if (sw > 0) {
+                    X = at<double>(p.o_theta2);
+                    CK(gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]),
+                            ddyn(k + 2, e[k + 1]), 0, 0, 0, e[k + 1] * c[k + 2], c[k] * e[k], P_F64));
+                }
+                JacobiDesc d = jac(X, at<double>(p.o_Q), ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), k + 1, mr, st.tol,
                                    st.trunc_mode, step);
-                CK(launch_jacobi(d, e[k + 1] * c[k + 2], c[k] * e[k], nullptr, at<int>(p.o_flag), s));
+                d.basis = at<double>(p.o_basis[k]);
+                CK(jac_launch(d, e[k + 1] * c[k + 2], c[k] * e[k]));
                 // Lenv[k+1] = Q XL[k]
                 CK(gemm(at(p.o_Q), T_F64, at(p.o_XL[k]), p.et, at(p.o_L[k + 1]), p.et, ddyn(k + 1), dconst(p.Dm[k + 1] * p.chiv[k + 1]),
                         ddyn(k, e[k]), 0, 0, 0, c[k + 1], p.Dm[k + 1] * p.chiv[k + 1], p.prec));
@@ -345,9 +370,14 @@ struct Enq {
                         ddyn(k + 2, e[k + 1]), dconst(p.Dm[k + 1] * p.chiv[k + 1]), 0, 0, 0, c[k] * e[k],
                         e[k + 1] * c[k + 2], p.prec));
                 const int mr = std::min(st.max_bond, c[k + 1]);
-                JacobiDesc d = jac(theta, at<double>(p.o_psi[k + 1]), ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), k + 1, mr,
+                // warm start from the left singular basis of this pass's left-to-right visit
+                double* X = at<double>(p.o_theta2);
+                CK(gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]),
+                        ddyn(k, e[k]), 0, 0, 0, c[k] * e[k], e[k + 1] * c[k + 2], P_F64));
+                JacobiDesc d = jac(X, at<double>(p.o_psi[k + 1]), ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), k + 1, mr,
                                    st.tol, st.trunc_mode, step);
-                CK(launch_jacobi(d, c[k] * e[k], e[k + 1] * c[k + 2], nullptr, at<int>(p.o_flag), s));
+                d.basis = at<double>(p.o_basis[k]);
+                CK(jac_launch(d, c[k] * e[k], e[k + 1] * c[k + 2]));
                 CK(env_R(k + 1, at(p.o_XR[k + 1]), at(p.o_R[k + 1]), p.et, p.prec));
                 ++step;
             }
@@ -402,6 +432,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
         SMPS_HIP(c, hipMemcpyAsync(c->log_sweeps.data(), q.at(p.o_lsweeps), 4 * steps, hipMemcpyDeviceToHost, q.s));
     }
     SMPS_HIP(c, hipStreamSynchronize(q.s));
+    prof_collect(c);
     if (status) return fail(c, SMPS_ENUMERIC, "non-finite values in a two-site tensor or the result");
     std::vector<int> bonds(hd.begin(), hd.begin() + L + 1);
     bonds[0] = bonds[L] = 1;
@@ -437,6 +468,7 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
     int rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     Enq q{p, U, v, st, c->arena, c->stream, (int*)(c->arena + p.o_dims)};
+    q.ctx = c;
     hipError_t e = q.run();
     if (e != hipSuccess)
         return fail(c, SMPS_EHIP, std::string("enqueue failed at ") + q.where + ": " + hipGetErrorString(e));
