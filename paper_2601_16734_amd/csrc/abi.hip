@@ -164,6 +164,8 @@ int smps_ctx_destroy(smps_ctx* c) {
     if (c->pinned) hipHostFree(c->pinned);
     for (auto& kv : c->pool) hipFree(kv.second);
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    batch_cache_free(c);
+    if (c->out_desc) hipFree(c->out_desc);
     mlp_free(c);
     delete c;
     return SMPS_OK;

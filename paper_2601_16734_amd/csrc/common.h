@@ -90,6 +90,8 @@ struct JacobiDesc {
     double* fro2;        // blocked path: ||X||_F^2 (device scalar, filled by the launcher)
     double* basis;       // len x len: all normalised vectors when they span R^len, else the
                          // identity; pre-rotates the next factorization at this bond (nullable)
+    int bs, nblk;        // blocked path: vectors per block, number of blocks (even)
+    int* done;           // blocked path, batched: set once a sweep rotated nothing
 };
 
 }  // namespace smps
@@ -107,6 +109,41 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
 size_t jacobi_work_doubles(int nvec_cap, int len_cap);
 hipError_t jacobi_init(int device);
 int jacobi_lds_limit();
+int jacobi_lds_class(int len_cap);
+size_t jacobi_lds_bytes(int nvec_cap, int len_cap);
+void jacobi_panel_params(int nvec_cap, int len_cap, int* bs, int* nblk);
+hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s);
+hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk, int max_rows,
+                                       int len_cap, size_t shm, int sweeps, hipStream_t s);
+hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
+                               hipStream_t s, int prec);
+hipError_t launch_left_mpo_batched(const LeftMpoDesc* arr, int count, const LeftMpoDesc& types, int a_cap,
+                                   int ny_cap, int nB_max, hipStream_t s);
+hipError_t launch_right_mpo_batched(const RightMpoDesc* arr, int count, const RightMpoDesc& types, int c_cap,
+                                    int nx_cap, int nB_max, hipStream_t s);
+// copies of count = a * b doubles per descriptor (dims from each descriptor's array)
+struct CopyDesc {
+    const double* src;
+    double* dst;
+    const int* dims;
+    DimExpr a, b;
+};
+hipError_t launch_copy_batched(const CopyDesc* arr, int count, int cap, hipStream_t s);
+// small per-problem scalar work: dims[to] = dims[from]
+struct IntCopyDesc {
+    int* dims;
+    int from, to;
+};
+hipError_t launch_copy_int_batched(const IntCopyDesc* arr, int count, hipStream_t s);
+// sum of squares of n = eval(nexpr) doubles into out, and a finiteness check into status
+struct NormDesc {
+    const double* x;
+    const int* dims;
+    DimExpr n;
+    double* out;
+    int* status;
+};
+hipError_t launch_norm_check_batched(const NormDesc* arr, int count, hipStream_t s);
 bool jacobi_fits_lds(int nvec_cap, int len_cap);
 hipError_t launch_copy(const double* src, double* dst, const int* dims, DimExpr a, DimExpr b, int cap,
                        hipStream_t s);

@@ -52,15 +52,17 @@ __device__ __forceinline__ double opA(const void* A, int ta, int M, int K, int r
 // FP64 / FP32 path: BK = 16, LDS holds A as [k][m] and B as [k][n].
 // ---------------------------------------------------------------------------
 template <int PREC, typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g) {
+__global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc* garr) {
+    // one descriptor, or one per blockIdx.z (batched launch over independent problems)
+    const GemmDesc g = garr ? garr[blockIdx.z] : g0;
     using CT = typename std::conditional<PREC == P_F64, double, float>::type;
     constexpr int BK = 16;
     const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (m0 >= M || n0 >= N) return;
-    const void* A = (const char*)g.A + (size_t)blockIdx.z * g.sA * sizeof(TA);
-    const void* B = (const char*)g.B + (size_t)blockIdx.z * g.sB * sizeof(TB);
-    void* C = (char*)g.C + (size_t)blockIdx.z * g.sC * sizeof(TC);
+    const void* A = g.A;
+    const void* B = g.B;
+    void* C = g.C;
 
     __shared__ CT As[BK][BM + 4];
     __shared__ CT Bs[BK][BN + 4];
@@ -131,15 +133,17 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g) {
 // lane's eight consecutive k values are one 16-byte read.
 // ---------------------------------------------------------------------------
 template <int PREC, typename TA, typename TB, typename TC>
-__global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g) {
+__global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDesc* garr) {
+    // one descriptor, or one per blockIdx.z (batched launch over independent problems)
+    const GemmDesc g = garr ? garr[blockIdx.z] : g0;
     constexpr int BK = 32, LD = BK + 8;
     constexpr bool SPLIT = (PREC == P_BF16X3);
     const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (m0 >= M || n0 >= N) return;
-    const void* A = (const char*)g.A + (size_t)blockIdx.z * g.sA * sizeof(TA);
-    const void* B = (const char*)g.B + (size_t)blockIdx.z * g.sB * sizeof(TB);
-    void* C = (char*)g.C + (size_t)blockIdx.z * g.sC * sizeof(TC);
+    const void* A = g.A;
+    const void* B = g.B;
+    void* C = g.C;
 
     __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LD];
     __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LD];
@@ -214,43 +218,50 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g) {
 }
 
 template <int PREC, typename TA, typename TB, typename TC>
-static void launch_t(const GemmDesc& g, dim3 grid, hipStream_t s) {
+static void launch_t(const GemmDesc& g, const GemmDesc* arr, dim3 grid, hipStream_t s) {
     if constexpr (PREC == P_F64 || PREC == P_F32)
-        hipLaunchKernelGGL((gemm_kernel_f<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel_f<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g, arr);
     else
-        hipLaunchKernelGGL((gemm_kernel_bf<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel_bf<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g, arr);
 }
 
 template <int PREC>
-static void launch_prec(const GemmDesc& g, dim3 grid, hipStream_t s) {
+static void launch_prec(const GemmDesc& g, const GemmDesc* arr, dim3 grid, hipStream_t s) {
     const int code = (g.a_type << 2) | (g.b_type << 1) | g.c_type;
     switch (code) {
-        case 0: launch_t<PREC, double, double, double>(g, grid, s); break;
-        case 1: launch_t<PREC, double, double, float>(g, grid, s); break;
-        case 2: launch_t<PREC, double, float, double>(g, grid, s); break;
-        case 3: launch_t<PREC, double, float, float>(g, grid, s); break;
-        case 4: launch_t<PREC, float, double, double>(g, grid, s); break;
-        case 5: launch_t<PREC, float, double, float>(g, grid, s); break;
-        case 6: launch_t<PREC, float, float, double>(g, grid, s); break;
-        default: launch_t<PREC, float, float, float>(g, grid, s); break;
+        case 0: launch_t<PREC, double, double, double>(g, arr, grid, s); break;
+        case 1: launch_t<PREC, double, double, float>(g, arr, grid, s); break;
+        case 2: launch_t<PREC, double, float, double>(g, arr, grid, s); break;
+        case 3: launch_t<PREC, double, float, float>(g, arr, grid, s); break;
+        case 4: launch_t<PREC, float, double, double>(g, arr, grid, s); break;
+        case 5: launch_t<PREC, float, double, float>(g, arr, grid, s); break;
+        case 6: launch_t<PREC, float, float, double>(g, arr, grid, s); break;
+        default: launch_t<PREC, float, float, float>(g, arr, grid, s); break;
     }
 }
 
-hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec) {
-    if (M_cap <= 0 || N_cap <= 0 || batch <= 0) return hipSuccess;
-    dim3 grid((N_cap + BN - 1) / BN, (M_cap + BM - 1) / BM, batch);
+static hipError_t launch_any(const GemmDesc& g, const GemmDesc* arr, int M_cap, int N_cap, int count, hipStream_t s,
+                             int prec) {
+    if (M_cap <= 0 || N_cap <= 0 || count <= 0) return hipSuccess;
+    dim3 grid((N_cap + BN - 1) / BN, (M_cap + BM - 1) / BM, count);
     switch (prec) {
-        case P_F64: {
-            // the FP64 path keeps every operand in FP64
-            GemmDesc h = g;
-            launch_prec<P_F64>(h, grid, s);
-            break;
-        }
-        case P_F32: launch_prec<P_F32>(g, grid, s); break;
-        case P_BF16X3: launch_prec<P_BF16X3>(g, grid, s); break;
-        default: launch_prec<P_BF16>(g, grid, s); break;
+        case P_F64: launch_prec<P_F64>(g, arr, grid, s); break;
+        case P_F32: launch_prec<P_F32>(g, arr, grid, s); break;
+        case P_BF16X3: launch_prec<P_BF16X3>(g, arr, grid, s); break;
+        default: launch_prec<P_BF16>(g, arr, grid, s); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec) {
+    (void)batch;
+    return launch_any(g, nullptr, M_cap, N_cap, 1, s, prec);
+}
+
+// `types` carries a_type, b_type, c_type (shared by every descriptor of the launch)
+hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
+                               hipStream_t s, int prec) {
+    return launch_any(types, d_descs, M_cap, N_cap, count, s, prec);
 }
 
 }  // namespace smps

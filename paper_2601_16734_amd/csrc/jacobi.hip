@@ -21,6 +21,8 @@
 //   the kept rows normalised.
 
 #include <cfloat>
+#include <cstdio>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -76,7 +78,7 @@ __device__ __forceinline__ double row_sum16(double x) {
 // Returns (block-uniform) the number of sweeps that applied a rotation.
 template <int E>
 __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double total2,
-                             int true_len) {
+                             int true_len, int max_sweeps = JAC_MAX_SWEEPS) {
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
     // cosine threshold: rounding in a length-n dot product is ~eps*sqrt(n); eps*n leaves margin
@@ -86,7 +88,7 @@ __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, in
     constexpr int g = 16;
     const int gl = tid & (g - 1), gi = tid / g, ngroups = JT / g;
     int any = 0;
-    for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         for (int j = gi; j < nv; j += ngroups) {
             const double* w = W + j * ld;
             double a0 = 0.0, a1 = 0.0;
@@ -300,8 +302,9 @@ __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, cons
 }
 
 template <int E>
-__global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d) {
+__global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const JacobiDesc* arr) {
     extern __shared__ double sm[];
+    const JacobiDesc d = arr ? arr[blockIdx.x] : d0;  // batched: one factorization per workgroup
     __shared__ int s_flag, s_bad;
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
@@ -357,11 +360,16 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d) {
 
 // One round of the blocked path: workgroup i takes the block pair of
 // tournament position i, orthogonalises the union in LDS, writes it back.
-template <int E>
-__global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d, int bs, int nblk2, int rd) {
+// Batched launches index the factorization by blockIdx.y; a factorization
+// whose `done` flag is set (converged in an earlier sweep) exits at once.
+__global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr, int rd) {
     extern __shared__ double sm[];
     __shared__ int s_flag, s_bad;
     __shared__ double s_nrm[64];
+    const JacobiDesc d = arr ? arr[blockIdx.y] : d0;
+    const int bs = d.bs, nblk2 = d.nblk;
+    if (rd >= nblk2 - 1 || (int)blockIdx.x >= nblk2 / 2) return;
+    if (d.done && *d.done) return;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     const int bp = tourney(blockIdx.x, rd, nblk2), bq = tourney(nblk2 - 1 - blockIdx.x, rd, nblk2);
     // vectors of the two blocks that exist
@@ -389,7 +397,8 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d, int bs, 
         if (tid == 0 && d.status) *d.status = 1;
         return;
     }
-    const bool any = jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, *d.fro2, len) > 0;
+    // one inner sweep per round: the outer tournament then acts as one cyclic ordering
+    const bool any = jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, *d.fro2, len, 1) > 0;
     if (!any) return;
     for (size_t e = tid; e < (size_t)nloc * len; e += JT) {
         const int j = (int)(e / len), l = (int)(e % len);
@@ -400,7 +409,8 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d, int bs, 
 }
 
 // Blocked path finish: select on the vectors in global memory.
-__global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d) {
+__global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+    const JacobiDesc d = arr ? arr[blockIdx.x] : d0;
     __shared__ double sig_raw[SEL_MAX];
     __shared__ double sig_sorted[SEL_MAX];
     __shared__ int perm_s[SEL_MAX];
@@ -410,7 +420,8 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d) {
     for (int j = threadIdx.x; j < nv; j += JT) d.perm[j] = perm_s[j];
 }
 
-__global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d) {
+__global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+    const JacobiDesc d = arr ? arr[blockIdx.z] : d0;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     const int r = d.dims_out[d.rank_idx];
     const int i = blockIdx.y;
@@ -431,8 +442,31 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d) {
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
+// Batched blocked path, between sweeps: a factorization that rotated nothing
+// in the sweep just finished is done; clear the rotation flags.
+__global__ void jacobi_sweep_end_kernel(const JacobiDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        if (*arr[i].conv == 0) *arr[i].done = 1;
+        *arr[i].conv = 0;
+    }
+}
+
+// After the sweep budget: a factorization still rotating is reported (status bit 2).
+__global__ void jacobi_check_done_kernel(const JacobiDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        if (*arr[i].done == 0) atomicOr(arr[i].status, 2);
+}
+
+__global__ void jacobi_reset_kernel(const JacobiDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        *arr[i].conv = 0;
+        *arr[i].done = 0;
+    }
+}
+
 // ||X||_F^2 for the blocked path's rank floor: per-vector sums in vector order.
-__global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d) {
+__global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+    const JacobiDesc d = arr ? arr[blockIdx.x] : d0;
     __shared__ double part[SEL_MAX];
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     const int tid = threadIdx.x, gl = tid & 15, gi = tid >> 4;
@@ -461,12 +495,10 @@ hipError_t jacobi_init(int device) {
     lim = lim < LDS_BYTES ? lim : LDS_BYTES;
     // the dynamic part may use what the kernels' static LDS leaves free
     size_t stat = 0;
-    const void* kernels[] = {(const void*)jacobi_lds_kernel<0>,   (const void*)jacobi_lds_kernel<1>,
-                             (const void*)jacobi_lds_kernel<2>,   (const void*)jacobi_lds_kernel<4>,
-                             (const void*)jacobi_lds_kernel<8>,   (const void*)jacobi_lds_kernel<16>,
-                             (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
-                             (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
-                             (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>};
+    const void* kernels[] = {(const void*)jacobi_lds_kernel<0>, (const void*)jacobi_lds_kernel<1>,
+                             (const void*)jacobi_lds_kernel<2>, (const void*)jacobi_lds_kernel<4>,
+                             (const void*)jacobi_lds_kernel<8>, (const void*)jacobi_lds_kernel<16>,
+                             (const void*)jacobi_panel_kernel};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -491,54 +523,59 @@ static size_t lds_need(int nvec, int len) {
     return sizeof(double) * ((size_t)nvec * ld + 2 * (size_t)nvec) + sizeof(int) * (size_t)nvec + 64;
 }
 
-bool jacobi_fits_lds(int nvec_cap, int len_cap) { return lds_need(nvec_cap, len_cap) <= (size_t)g_lds_bytes - 1024; }
+bool jacobi_fits_lds(int nvec_cap, int len_cap) {
+    return nvec_cap <= SEL_MAX && lds_need(nvec_cap, len_cap) <= (size_t)g_lds_bytes - 1024;
+}
 
-static int panel_bs(int len_cap) {
+int jacobi_lds_class(int len_cap) { return elems_for(len_cap); }
+size_t jacobi_lds_bytes(int nvec_cap, int len_cap) { return lds_need(nvec_cap, len_cap); }
+
+void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) {
     int bs = (int)((g_lds_bytes - 4096) / (2 * sizeof(double) * (size_t)len_cap));
     if (bs > 32) bs = 32;
     if (bs < 1) bs = 1;
-    return bs;
+    int nblk = (nvec_cap + bs - 1) / bs;
+    if (nblk & 1) ++nblk;
+    *bs_out = bs;
+    *nblk_out = nblk;
 }
 
-size_t jacobi_work_doubles(int nvec_cap, int len_cap) { return 0; }
+size_t jacobi_work_doubles(int, int) { return 0; }
+
+static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
+    const dim3 g(count), b(JT);
+    switch (E) {
+        case 1: hipLaunchKernelGGL(jacobi_lds_kernel<1>, g, b, shm, s, d, arr); break;
+        case 2: hipLaunchKernelGGL(jacobi_lds_kernel<2>, g, b, shm, s, d, arr); break;
+        case 4: hipLaunchKernelGGL(jacobi_lds_kernel<4>, g, b, shm, s, d, arr); break;
+        case 8: hipLaunchKernelGGL(jacobi_lds_kernel<8>, g, b, shm, s, d, arr); break;
+        case 16: hipLaunchKernelGGL(jacobi_lds_kernel<16>, g, b, shm, s, d, arr); break;
+        default: hipLaunchKernelGGL(jacobi_lds_kernel<0>, g, b, shm, s, d, arr); break;
+    }
+}
 
 hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
     (void)work;
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
     if (jacobi_fits_lds(nvec_cap, len_cap)) {
-        const size_t shm = lds_need(nvec_cap, len_cap);
-        switch (elems_for(len_cap)) {
-            case 1: hipLaunchKernelGGL(jacobi_lds_kernel<1>, dim3(1), dim3(JT), shm, s, d); break;
-            case 2: hipLaunchKernelGGL(jacobi_lds_kernel<2>, dim3(1), dim3(JT), shm, s, d); break;
-            case 4: hipLaunchKernelGGL(jacobi_lds_kernel<4>, dim3(1), dim3(JT), shm, s, d); break;
-            case 8: hipLaunchKernelGGL(jacobi_lds_kernel<8>, dim3(1), dim3(JT), shm, s, d); break;
-            case 16: hipLaunchKernelGGL(jacobi_lds_kernel<16>, dim3(1), dim3(JT), shm, s, d); break;
-            default: hipLaunchKernelGGL(jacobi_lds_kernel<0>, dim3(1), dim3(JT), shm, s, d); break;
-        }
+        launch_lds(d, nullptr, 1, elems_for(len_cap), lds_need(nvec_cap, len_cap), s);
         return hipGetLastError();
     }
     if (nvec_cap > SEL_MAX) return hipErrorInvalidValue;
-    // blocked path; `flags` is one device int used as the "rotated" flag
-    const int bs = panel_bs(len_cap);
-    int nblk = (nvec_cap + bs - 1) / bs;
-    if (nblk & 1) ++nblk;
-    const size_t shm = sizeof(double) * 2 * (size_t)bs * len_cap;
-    const int E = elems_for(len_cap);
+    // blocked path; `flags` is one device int used as the "rotated" flag, and
+    // the host reads it after every sweep
     JacobiDesc dd = d;
+    jacobi_panel_params(nvec_cap, len_cap, &dd.bs, &dd.nblk);
     dd.conv = flags;
+    dd.done = nullptr;
     if (!dd.fro2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd);
-    for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
+    const size_t shm = sizeof(double) * 2 * (size_t)dd.bs * len_cap;
+    hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
+    int sweep = 0;
+    for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
         hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
-        for (int rd = 0; rd < nblk - 1; ++rd)
-            switch (E) {
-                case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-                case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-                case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-                case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-                case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-                default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, dim3(nblk / 2), dim3(JT), shm, s, dd, bs, nblk, rd); break;
-            }
+        for (int rd = 0; rd < dd.nblk - 1; ++rd)
+            hipLaunchKernelGGL(jacobi_panel_kernel, dim3(dd.nblk / 2, 1), dim3(JT), shm, s, dd, nullptr, rd);
         int h = 0;
         hipError_t e = hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
@@ -546,9 +583,42 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
         if (e != hipSuccess) return e;
         if (!h) break;
     }
-    hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd);
+    static const bool dbg = getenv("SMPS_DEBUG_BLOCKED") != nullptr;
+    if (dbg) fprintf(stderr, "blocked jacobi: nvec_cap %d len_cap %d bs %d nblk %d sweeps %d\n", nvec_cap, len_cap,
+                     dd.bs, dd.nblk, sweep + 1);
+    hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
     const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
-    hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows), dim3(256), 0, s, dd);
+    hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
+    return hipGetLastError();
+}
+
+// ---- batched forms (descriptor arrays on the device) -----------------------
+
+hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    JacobiDesc none{};
+    launch_lds(none, arr, count, E, shm, s);
+    return hipGetLastError();
+}
+
+// Every descriptor carries bs / nblk / conv / done / fro2.  A fixed number of
+// sweeps is enqueued (no host read-back, so the sequence can be captured in a
+// graph); factorizations that converge earlier skip the remaining rounds.
+hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk,
+                                       int max_rows, int len_cap, size_t shm, int sweeps, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    JacobiDesc none{};
+    hipLaunchKernelGGL(jacobi_reset_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    hipLaunchKernelGGL(fro2_kernel, dim3(count), dim3(JT), 0, s, none, arr);
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int rd = 0; rd < max_nblk - 1; ++rd)
+            hipLaunchKernelGGL(jacobi_panel_kernel, dim3(max_pairs, count), dim3(JT), shm, s, none, arr, rd);
+        hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    }
+    hipLaunchKernelGGL(jacobi_check_done_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    hipLaunchKernelGGL(jacobi_select_kernel, dim3(count), dim3(JT), 0, s, none, arr);
+    hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, max_rows, count), dim3(256), 0, s, none,
+                       arr);
     return hipGetLastError();
 }
 

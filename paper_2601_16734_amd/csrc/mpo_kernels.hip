@@ -17,8 +17,9 @@ __device__ __forceinline__ double ldx(const void* p, size_t i) {
 // Y[a][t][b'][y] = sum_{b,q} X[a][b][q][y] * B[b][t][q][b']
 // X holds (environment x v-site) with rows (a, b) and columns (q, y).
 template <typename TX, typename TY>
-__global__ __launch_bounds__(128) void left_mpo_kernel(LeftMpoDesc d) {
+__global__ __launch_bounds__(128) void left_mpo_kernel(LeftMpoDesc d0, const LeftMpoDesc* arr) {
     extern __shared__ double Bs[];
+    const LeftMpoDesc d = arr ? arr[blockIdx.z] : d0;
     const int nB = d.Dl * d.e * d.d * d.Dr;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) Bs[i] = d.B[i];
     __syncthreads();
@@ -42,8 +43,9 @@ __global__ __launch_bounds__(128) void left_mpo_kernel(LeftMpoDesc d) {
 // Y[b][x][t][c] = sum_{q,b'} B[b][t][q][b'] * X[x][q][c][b']
 // X holds (v-site x environment) with rows (x, q) and columns (c, b').
 template <typename TX, typename TY>
-__global__ __launch_bounds__(128) void right_mpo_kernel(RightMpoDesc d) {
+__global__ __launch_bounds__(128) void right_mpo_kernel(RightMpoDesc d0, const RightMpoDesc* arr) {
     extern __shared__ double Bs[];
+    const RightMpoDesc d = arr ? arr[blockIdx.z] : d0;
     const int nB = d.Dl * d.e * d.d * d.Dr;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) Bs[i] = d.B[i];
     __syncthreads();
@@ -63,34 +65,53 @@ __global__ __launch_bounds__(128) void right_mpo_kernel(RightMpoDesc d) {
         }
 }
 
-hipError_t launch_left_mpo(const LeftMpoDesc& d, int a_cap, hipStream_t s) {
-    if (a_cap <= 0 || d.ny <= 0) return hipSuccess;
-    dim3 grid((d.ny + 127) / 128, a_cap);
-    const size_t shm = sizeof(double) * d.Dl * d.e * d.d * d.Dr;
+static hipError_t left_any(const LeftMpoDesc& d, const LeftMpoDesc* arr, int count, int a_cap, int ny_cap,
+                           size_t shm, hipStream_t s) {
+    if (a_cap <= 0 || ny_cap <= 0 || count <= 0) return hipSuccess;
+    dim3 grid((ny_cap + 127) / 128, a_cap, count);
     if (d.x_type == T_F64 && d.y_type == T_F64)
-        hipLaunchKernelGGL((left_mpo_kernel<double, double>), grid, dim3(128), shm, s, d);
+        hipLaunchKernelGGL((left_mpo_kernel<double, double>), grid, dim3(128), shm, s, d, arr);
     else if (d.x_type == T_F32 && d.y_type == T_F32)
-        hipLaunchKernelGGL((left_mpo_kernel<float, float>), grid, dim3(128), shm, s, d);
+        hipLaunchKernelGGL((left_mpo_kernel<float, float>), grid, dim3(128), shm, s, d, arr);
     else if (d.x_type == T_F64)
-        hipLaunchKernelGGL((left_mpo_kernel<double, float>), grid, dim3(128), shm, s, d);
+        hipLaunchKernelGGL((left_mpo_kernel<double, float>), grid, dim3(128), shm, s, d, arr);
     else
-        hipLaunchKernelGGL((left_mpo_kernel<float, double>), grid, dim3(128), shm, s, d);
+        hipLaunchKernelGGL((left_mpo_kernel<float, double>), grid, dim3(128), shm, s, d, arr);
+    return hipGetLastError();
+}
+
+hipError_t launch_left_mpo(const LeftMpoDesc& d, int a_cap, hipStream_t s) {
+    return left_any(d, nullptr, 1, a_cap, d.ny, sizeof(double) * d.Dl * d.e * d.d * d.Dr, s);
+}
+
+// `types` supplies x_type / y_type; caps are maxima over the descriptors
+hipError_t launch_left_mpo_batched(const LeftMpoDesc* arr, int count, const LeftMpoDesc& types, int a_cap,
+                                   int ny_cap, int nB_max, hipStream_t s) {
+    return left_any(types, arr, count, a_cap, ny_cap, sizeof(double) * nB_max, s);
+}
+
+static hipError_t right_any(const RightMpoDesc& d, const RightMpoDesc* arr, int count, int c_cap, int nx_cap,
+                            size_t shm, hipStream_t s) {
+    if (c_cap <= 0 || nx_cap <= 0 || count <= 0) return hipSuccess;
+    dim3 grid((c_cap + 127) / 128, nx_cap, count);
+    if (d.x_type == T_F64 && d.y_type == T_F64)
+        hipLaunchKernelGGL((right_mpo_kernel<double, double>), grid, dim3(128), shm, s, d, arr);
+    else if (d.x_type == T_F32 && d.y_type == T_F32)
+        hipLaunchKernelGGL((right_mpo_kernel<float, float>), grid, dim3(128), shm, s, d, arr);
+    else if (d.x_type == T_F64)
+        hipLaunchKernelGGL((right_mpo_kernel<double, float>), grid, dim3(128), shm, s, d, arr);
+    else
+        hipLaunchKernelGGL((right_mpo_kernel<float, double>), grid, dim3(128), shm, s, d, arr);
     return hipGetLastError();
 }
 
 hipError_t launch_right_mpo(const RightMpoDesc& d, int c_cap, hipStream_t s) {
-    if (c_cap <= 0 || d.nx <= 0) return hipSuccess;
-    dim3 grid((c_cap + 127) / 128, d.nx);
-    const size_t shm = sizeof(double) * d.Dl * d.e * d.d * d.Dr;
-    if (d.x_type == T_F64 && d.y_type == T_F64)
-        hipLaunchKernelGGL((right_mpo_kernel<double, double>), grid, dim3(128), shm, s, d);
-    else if (d.x_type == T_F32 && d.y_type == T_F32)
-        hipLaunchKernelGGL((right_mpo_kernel<float, float>), grid, dim3(128), shm, s, d);
-    else if (d.x_type == T_F64)
-        hipLaunchKernelGGL((right_mpo_kernel<double, float>), grid, dim3(128), shm, s, d);
-    else
-        hipLaunchKernelGGL((right_mpo_kernel<float, double>), grid, dim3(128), shm, s, d);
-    return hipGetLastError();
+    return right_any(d, nullptr, 1, c_cap, d.nx, sizeof(double) * d.Dl * d.e * d.d * d.Dr, s);
+}
+
+hipError_t launch_right_mpo_batched(const RightMpoDesc* arr, int count, const RightMpoDesc& types, int c_cap,
+                                    int nx_cap, int nB_max, hipStream_t s) {
+    return right_any(types, arr, count, c_cap, nx_cap, sizeof(double) * nB_max, s);
 }
 
 }  // namespace smps

@@ -25,6 +25,11 @@ struct smps_ctx {
     std::vector<int> log_rank, log_sweeps;
     // rank predictor state (device buffers, see mlp.hip)
     void* mlp = nullptr;
+    // batched execution: captured graph of the last batch shape, and the
+    // device buffer of the output-copy descriptors
+    void* batch = nullptr;
+    char* out_desc = nullptr;
+    size_t out_desc_bytes = 0;
     // optional per-category kernel timing (events recorded on the stream)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -78,6 +83,7 @@ struct ApplyProblem {
 int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
               double* trunc_err);
 void mlp_free(smps_ctx* c);
+void batch_cache_free(smps_ctx* c);
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                       const smps_strategy& st, smps_mps** out, double* trunc_err);
 }  // namespace smps

@@ -1,5 +1,7 @@
 // The apply + compression sweep (Sec. 2.3 Eq. simplification, Sec. 2.4.2,
-// Sec. 2.5): host-side planning and the enqueue of every kernel.
+// Sec. 2.5): host-side planning, the operation sequence of one problem, and
+// its execution -- launched directly for one problem, or merged across many
+// independent problems into batched launches captured in one HIP graph.
 //
 // Layouts (compact, row-major, live bond dimensions):
 //   psi[k]  (chi_k, e_k, chi_{k+1})                        FP64
@@ -18,6 +20,8 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 #include "runtime.h"
 
@@ -53,7 +57,7 @@ struct Plan {
     size_t es = 8;      // its size
     std::vector<int> e, dv, Dm, chiv, capb;
     // offsets into the workspace
-    size_t o_dims, o_status, o_flag, o_norm2, o_fro2;
+    size_t o_dims, o_status, o_flag, o_done, o_norm2, o_fro2;
     std::vector<size_t> o_psi, o_L, o_R, o_XL, o_XR, o_basis;
     size_t o_tmp, o_theta, o_theta2, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
     size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
@@ -63,7 +67,7 @@ struct Plan {
     int max_nvec = 0;
 };
 
-static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, Layout& lay) {
+void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, Layout& lay) {
     const int L = v->L;
     p.L = L;
     p.prec = st.precision;
@@ -100,6 +104,7 @@ static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const sm
     p.o_flag = lay.add(sizeof(int));
     p.o_norm2 = lay.add(sizeof(double));
     p.o_fro2 = lay.add(sizeof(double));
+    p.o_done = lay.add(sizeof(int));
     p.o_psi.resize(L);
     p.o_L.resize(L + 1);
     p.o_R.resize(L + 1);
@@ -164,7 +169,35 @@ static void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const sm
     }
 }
 
-// Kernels of one problem, enqueued on stream s with the workspace at base.
+
+// ---------------------------------------------------------------------------
+// Operations.  The sequence of one problem is produced by Enq::run(); every
+// operation carries an alignment tag (major phase, step j inside the phase,
+// slot inside the step).  Problems of different lengths produce the same slot
+// pattern for the same (major, j), so equal tags across problems can share a
+// launch.
+// ---------------------------------------------------------------------------
+
+enum OpKind { OP_GEMM, OP_LEFT, OP_RIGHT, OP_JAC, OP_COPY, OP_INTCOPY, OP_SETINTS, OP_FILL, OP_NORM };
+
+struct Op {
+    OpKind kind;
+    int major = 0, j = 0, slot = 0;
+    GemmDesc g{};
+    LeftMpoDesc l{};
+    RightMpoDesc r{};
+    JacobiDesc jd{};
+    CopyDesc cp{};
+    IntCopyDesc ic{};
+    NormDesc nd{};
+    int cap0 = 0, cap1 = 0, prec = 0;
+    int* set_base = nullptr;
+    std::vector<int> set_vals;
+    void* fill_dst = nullptr;
+    int fill_type = 0;
+    double fill_val = 0.0;
+};
+
 struct Enq {
     const Plan& p;
     const smps_mpo* U;
@@ -173,25 +206,59 @@ struct Enq {
     char* base;
     hipStream_t s;
     int* dims;
-    mutable const char* where = "";
     smps_ctx* ctx = nullptr;
-
-    // exact factorization, timed as category 0 when profiling is on
-    hipError_t jac_launch(const JacobiDesc& d, int nvec_cap, int len_cap) const {
-        const int tok = ctx ? prof_begin(ctx, s) : -1;
-        hipError_t e = launch_jacobi(d, nvec_cap, len_cap, nullptr, at<int>(p.o_flag), s);
-        if (ctx) prof_end(ctx, s, tok, 0);
-        return e;
-    }
+    std::vector<Op>* rec = nullptr;  // record instead of launching
+    mutable const char* where = "";
+    mutable int cur_major = 0, cur_j = 0, cur_slot = 0;
 
     template <typename T = void>
     T* at(size_t off) const { return (T*)(base + off); }
     const double* vsite(int k) const { return v->data + v->off[k]; }
     const double* usite(int k) const { return U->data + U->off[k]; }
+    double* centre() const { return p.et == T_F64 ? at<double>(p.o_XR[0]) : at<double>(p.o_XR64); }
+
+    void tag(int major, int j) const {
+        cur_major = major;
+        cur_j = j;
+        cur_slot = 0;
+    }
+
+    hipError_t emit(Op&& op) const {
+        op.major = cur_major;
+        op.j = cur_j;
+        op.slot = cur_slot++;
+        if (rec) {
+            rec->push_back(std::move(op));
+            return hipSuccess;
+        }
+        switch (op.kind) {
+            case OP_GEMM: return launch_gemm(op.g, op.cap0, op.cap1, 1, s, op.prec);
+            case OP_LEFT: return launch_left_mpo(op.l, op.cap0, s);
+            case OP_RIGHT: return launch_right_mpo(op.r, op.cap0, s);
+            case OP_JAC: {
+                const int tok = ctx ? prof_begin(ctx, s) : -1;
+                hipError_t e = launch_jacobi(op.jd, op.cap0, op.cap1, nullptr, at<int>(p.o_flag), s);
+                if (ctx) prof_end(ctx, s, tok, 0);
+                return e;
+            }
+            case OP_COPY: return launch_copy(op.cp.src, op.cp.dst, op.cp.dims, op.cp.a, op.cp.b, op.cap0, s);
+            case OP_INTCOPY: return launch_copy_int(op.ic.dims, op.ic.from, op.ic.to, s);
+            case OP_SETINTS: return launch_set_dims(op.set_base, op.set_vals.data(), (int)op.set_vals.size(), s);
+            case OP_FILL: return launch_fill_typed(op.fill_dst, op.fill_type, op.fill_val, 1, s);
+            case OP_NORM: {
+                hipError_t e = launch_sumsq(op.nd.x, op.nd.dims, op.nd.n, op.cap0, op.nd.out, s);
+                if (e != hipSuccess) return e;
+                return launch_check_finite(op.nd.x, op.nd.dims, op.nd.n, op.cap0, op.nd.status, s);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
 
     hipError_t gemm(const void* A, int ta_type, const void* B, int tb_type, void* C, int tc_type, DimExpr M,
                     DimExpr N, DimExpr K, int ta, int tb, int tc, int Mcap, int Ncap, int prec) const {
-        GemmDesc g{};
+        Op op;
+        op.kind = OP_GEMM;
+        GemmDesc& g = op.g;
         g.A = A;
         g.B = B;
         g.C = C;
@@ -206,7 +273,18 @@ struct Enq {
         g.b_type = tb_type;
         g.c_type = tc_type;
         g.alpha = 1.0;
-        return launch_gemm(g, Mcap, Ncap, 1, s, prec);
+        op.cap0 = Mcap;
+        op.cap1 = Ncap;
+        op.prec = prec;
+        return emit(std::move(op));
+    }
+
+    hipError_t copy(const double* src, double* dst, DimExpr a, DimExpr b, int cap) const {
+        Op op;
+        op.kind = OP_COPY;
+        op.cp = CopyDesc{src, dst, dims, a, b};
+        op.cap0 = cap;
+        return emit(std::move(op));
     }
 
     // XL[k] = (Lenv[k] A_k) B_k
@@ -216,7 +294,9 @@ struct Enq {
                             dconst(p.dv[k] * p.chiv[k + 1]), dconst(p.chiv[k]), 0, 0, 0, c[k] * p.Dm[k],
                             p.dv[k] * p.chiv[k + 1], p.prec);
         if (e != hipSuccess) return e;
-        LeftMpoDesc d{};
+        Op op;
+        op.kind = OP_LEFT;
+        LeftMpoDesc& d = op.l;
         d.X = at(p.o_tmp);
         d.Y = at(p.o_XL[k]);
         d.B = usite(k);
@@ -229,7 +309,8 @@ struct Enq {
         d.ny = p.chiv[k + 1];
         d.x_type = p.et;
         d.y_type = p.et;
-        return launch_left_mpo(d, c[k], s);
+        op.cap0 = c[k];
+        return emit(std::move(op));
     }
 
     // XR[k] = B_k (A_k Renv[k+1]^T), with Renv given explicitly (type rt)
@@ -239,7 +320,9 @@ struct Enq {
                             ddyn(k + 1, p.Dm[k + 1]), dconst(p.chiv[k + 1]), 0, 1, 0, p.chiv[k] * p.dv[k],
                             c[k + 1] * p.Dm[k + 1], prec);
         if (e != hipSuccess) return e;
-        RightMpoDesc d{};
+        Op op;
+        op.kind = OP_RIGHT;
+        RightMpoDesc& d = op.r;
         d.X = tmp;
         d.Y = XR;
         d.B = usite(k);
@@ -252,7 +335,8 @@ struct Enq {
         d.nx = p.chiv[k];
         d.x_type = rt;
         d.y_type = rt;
-        return launch_right_mpo(d, c[k + 1], s);
+        op.cap0 = c[k + 1];
+        return emit(std::move(op));
     }
 
     // Renv[k] = psi_k XR[k]^T
@@ -279,6 +363,8 @@ struct Enq {
         d.mode = mode;
         d.status = at<int>(p.o_status);
         d.fro2 = at<double>(p.o_fro2);
+        d.conv = at<int>(p.o_flag);
+        d.done = at<int>(p.o_done);
         if (step >= 0) {
             d.log_delta = at<double>(p.o_ldelta) + step;
             d.log_rank = at<int>(p.o_lrank) + step;
@@ -289,10 +375,20 @@ struct Enq {
         return d;
     }
 
+    hipError_t jacobi(const JacobiDesc& d, int nvec_cap, int len_cap) const {
+        Op op;
+        op.kind = OP_JAC;
+        op.jd = d;
+        op.cap0 = nvec_cap;
+        op.cap1 = len_cap;
+        return emit(std::move(op));
+    }
+
     hipError_t run() const {
         const int L = p.L;
         const auto& c = p.capb;
         const auto& e = p.e;
+        const int S = st.max_sweeps;
         hipError_t er;
 #define CK(x)                      \
     do {                           \
@@ -303,43 +399,76 @@ struct Enq {
         }                          \
     } while (0)
         // ---- guess psi = v, bond dims, flags
-        std::vector<int> hd(L + 2, 0);
-        for (int k = 0; k <= L; ++k) hd[k] = p.chiv[k];
-        CK(launch_set_dims(dims, hd.data(), L + 2, s));
-        CK(launch_zero_ints(at<int>(p.o_status), 1, s));
-        for (int k = 0; k < L; ++k)
-            CK(hipMemcpyAsync(at(p.o_psi[k]), vsite(k), 8 * v->site_size(k), hipMemcpyDeviceToDevice, s));
+        tag(0, 0);
+        {
+            Op op;
+            op.kind = OP_SETINTS;
+            op.set_base = dims;
+            op.set_vals.assign(L + 2, 0);
+            for (int k = 0; k <= L; ++k) op.set_vals[k] = p.chiv[k];
+            CK(emit(std::move(op)));
+        }
+        {
+            Op op;
+            op.kind = OP_SETINTS;
+            op.set_base = at<int>(p.o_status);
+            op.set_vals.assign(1, 0);
+            CK(emit(std::move(op)));
+        }
+        {
+            Op a;
+            a.kind = OP_FILL;
+            a.fill_dst = at(p.o_L[0]);
+            a.fill_type = p.et;
+            a.fill_val = 1.0;
+            CK(emit(std::move(a)));
+            Op b;
+            b.kind = OP_FILL;
+            b.fill_dst = at(p.o_R[L]);
+            b.fill_type = p.et;
+            b.fill_val = 1.0;
+            CK(emit(std::move(b)));
+        }
+        for (int k = 0; k < L; ++k) {
+            tag(0, 1 + k);
+            const int n = (int)v->site_size(k);
+            CK(copy(vsite(k), at<double>(p.o_psi[k]), dconst(n), dconst(1), n));
+        }
         // ---- right-canonical form (Sec. 2.3): psi_k = V^T, carry psi_k V into site k-1
         const int RS = L + 1;  // scratch slot for a new rank
         for (int k = L - 1; k >= 1; --k) {
+            tag(1, L - 1 - k);
             double* theta = at<double>(p.o_theta);
             double* Q = at<double>(p.o_Q);
             const int lenc = e[k] * c[k + 1];
-            CK(launch_copy(at<double>(p.o_psi[k]), theta, dims, ddyn(k), ddyn(k + 1, e[k]), c[k] * lenc, s));
+            CK(copy(at<double>(p.o_psi[k]), theta, ddyn(k), ddyn(k + 1, e[k]), c[k] * lenc));
             JacobiDesc d = jac(theta, Q, ddyn(k), ddyn(k + 1, e[k]), RS, c[k], 0.0, SMPS_TRUNC_REL_NORM2, -1);
-            CK(jac_launch(d, c[k], lenc));
+            CK(jacobi(d, c[k], lenc));
             // carry = psi_k Q^T  (chi_k x r)
             CK(gemm(at(p.o_psi[k]), T_F64, Q, T_F64, at(p.o_carry), T_F64, ddyn(k), ddyn(RS), ddyn(k + 1, e[k]),
                     0, 1, 0, c[k], c[k], P_F64));
             // tmpB = psi_{k-1} carry
             CK(gemm(at(p.o_psi[k - 1]), T_F64, at(p.o_carry), T_F64, at(p.o_tmpB), T_F64, ddyn(k - 1, e[k - 1]),
                     ddyn(RS), ddyn(k), 0, 0, 0, c[k - 1] * e[k - 1], c[k], P_F64));
-            CK(launch_copy(Q, at<double>(p.o_psi[k]), dims, ddyn(RS), ddyn(k + 1, e[k]), c[k] * lenc, s));
-            CK(launch_copy(at<double>(p.o_tmpB), at<double>(p.o_psi[k - 1]), dims, ddyn(k - 1, e[k - 1]), ddyn(RS),
-                           c[k - 1] * e[k - 1] * c[k], s));
-            CK(launch_copy_int(dims, RS, k, s));
+            CK(copy(Q, at<double>(p.o_psi[k]), ddyn(RS), ddyn(k + 1, e[k]), c[k] * lenc));
+            CK(copy(at<double>(p.o_tmpB), at<double>(p.o_psi[k - 1]), ddyn(k - 1, e[k - 1]), ddyn(RS),
+                    c[k - 1] * e[k - 1] * c[k]));
+            Op ic;
+            ic.kind = OP_INTCOPY;
+            ic.ic = IntCopyDesc{dims, RS, k};
+            CK(emit(std::move(ic)));
         }
-        // ---- boundary environments and the right environments of the guess
-        CK(launch_fill_typed(at(p.o_L[0]), p.et, 1.0, 1, s));
-        CK(launch_fill_typed(at(p.o_R[L]), p.et, 1.0, 1, s));
+        // ---- right environments of the guess
         for (int k = L - 1; k >= 1; --k) {
+            tag(2, L - 1 - k);
             CK(build_XR(k, at(p.o_R[k + 1]), at(p.o_tmp), at(p.o_XR[k]), p.et, p.prec));
             CK(env_R(k, at(p.o_XR[k]), at(p.o_R[k]), p.et, p.prec));
         }
         // ---- sweeps (Sec. 2.5)
         int step = 0;
-        for (int sw = 0; sw < st.max_sweeps; ++sw) {
+        for (int sw = 0; sw < S; ++sw) {
             for (int k = 0; k + 1 < L; ++k) {  // left to right
+                tag(3 + 2 * sw, k);
                 CK(build_XL(k));
                 double* theta = at<double>(p.o_theta);
                 CK(gemm(at(p.o_XL[k]), p.et, at(p.o_XR[k + 1]), p.et, theta, T_F64, ddyn(k, e[k]),
@@ -357,13 +486,15 @@ struct Enq {
                 JacobiDesc d = jac(X, at<double>(p.o_Q), ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), k + 1, mr, st.tol,
                                    st.trunc_mode, step);
                 d.basis = at<double>(p.o_basis[k]);
-                CK(jac_launch(d, e[k + 1] * c[k + 2], c[k] * e[k]));
+                CK(jacobi(d, e[k + 1] * c[k + 2], c[k] * e[k]));
                 // Lenv[k+1] = Q XL[k]
-                CK(gemm(at(p.o_Q), T_F64, at(p.o_XL[k]), p.et, at(p.o_L[k + 1]), p.et, ddyn(k + 1), dconst(p.Dm[k + 1] * p.chiv[k + 1]),
-                        ddyn(k, e[k]), 0, 0, 0, c[k + 1], p.Dm[k + 1] * p.chiv[k + 1], p.prec));
+                CK(gemm(at(p.o_Q), T_F64, at(p.o_XL[k]), p.et, at(p.o_L[k + 1]), p.et, ddyn(k + 1),
+                        dconst(p.Dm[k + 1] * p.chiv[k + 1]), ddyn(k, e[k]), 0, 0, 0, c[k + 1],
+                        p.Dm[k + 1] * p.chiv[k + 1], p.prec));
                 ++step;
             }
             for (int k = L - 2; k >= 0; --k) {  // right to left
+                tag(4 + 2 * sw, L - 2 - k);
                 CK(build_XR(k + 1, at(p.o_R[k + 2]), at(p.o_tmp), at(p.o_XR[k + 1]), p.et, p.prec));
                 double* theta = at<double>(p.o_theta);
                 CK(gemm(at(p.o_XL[k]), p.et, at(p.o_XR[k + 1]), p.et, theta, T_F64, ddyn(k, e[k]),
@@ -377,7 +508,7 @@ struct Enq {
                 JacobiDesc d = jac(X, at<double>(p.o_psi[k + 1]), ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), k + 1, mr,
                                    st.tol, st.trunc_mode, step);
                 d.basis = at<double>(p.o_basis[k]);
-                CK(jac_launch(d, c[k] * e[k], e[k + 1] * c[k + 2]));
+                CK(jacobi(d, c[k] * e[k], e[k + 1] * c[k + 2]));
                 CK(env_R(k + 1, at(p.o_XR[k + 1]), at(p.o_R[k + 1]), p.et, p.prec));
                 ++step;
             }
@@ -386,26 +517,44 @@ struct Enq {
         // final right isometries; in the mixed precisions the right
         // environments are rebuilt in FP64 first.
         if (p.et == T_F64) {
+            tag(4 + 2 * S, 0);
             CK(build_XR(0, at(p.o_R[1]), at(p.o_tmp), at(p.o_XR[0]), T_F64, P_F64));
         } else {
             double* Ra = at<double>(p.o_R64a);
             double* Rb = at<double>(p.o_R64b);
-            CK(launch_fill(Ra, 1.0, 1, s));
+            tag(3 + 2 * S, 0);
+            Op f;
+            f.kind = OP_FILL;
+            f.fill_dst = Ra;
+            f.fill_type = T_F64;
+            f.fill_val = 1.0;
+            CK(emit(std::move(f)));
             for (int k = L - 1; k >= 1; --k) {
+                tag(3 + 2 * S, 1 + (L - 1 - k));
                 CK(build_XR(k, Ra, at(p.o_Y64), at(p.o_XR64), T_F64, P_F64));
                 CK(env_R(k, at(p.o_XR64), Rb, T_F64, P_F64));
                 std::swap(Ra, Rb);
             }
+            tag(4 + 2 * S, 0);
             CK(build_XR(0, Ra, at(p.o_Y64), at(p.o_XR64), T_F64, P_F64));
         }
-        CK(launch_sumsq(centre(), dims, ddyn(1, e[0]), e[0] * c[1], at<double>(p.o_norm2), s));
-        CK(launch_check_finite(centre(), dims, ddyn(1, e[0]), e[0] * c[1], at<int>(p.o_status), s));
+        tag(5 + 2 * S, 0);
+        {
+            Op op;
+            op.kind = OP_NORM;
+            op.nd = NormDesc{centre(), dims, ddyn(1, e[0]), at<double>(p.o_norm2), at<int>(p.o_status)};
+            op.cap0 = e[0] * c[1];
+            CK(emit(std::move(op)));
+        }
 #undef CK
         return hipSuccess;
     }
-
-    double* centre() const { return p.et == T_F64 ? at<double>(p.o_XR[0]) : at<double>(p.o_XR64); }
 };
+
+static const char* status_message(int status) {
+    if (status & 1) return "non-finite values in a two-site tensor or the result";
+    return "a blocked factorization did not converge within its sweep budget";
+}
 
 // Read back the bonds and logs, and build the output handle.
 static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy& st, smps_mps** out,
@@ -433,7 +582,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     }
     SMPS_HIP(c, hipStreamSynchronize(q.s));
     prof_collect(c);
-    if (status) return fail(c, SMPS_ENUMERIC, "non-finite values in a two-site tensor or the result");
+    if (status) return fail(c, SMPS_ENUMERIC, status_message(status));
     std::vector<int> bonds(hd.begin(), hd.begin() + L + 1);
     bonds[0] = bonds[L] = 1;
     smps_mps* m = new_mps(c, L, p.e, bonds);
@@ -465,6 +614,8 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
     Plan p;
     Layout lay;
     plan_problem(p, U, v, st, lay);
+    if (p.max_nvec > 2048)
+        return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
     int rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     Enq q{p, U, v, st, c->arena, c->stream, (int*)(c->arena + p.o_dims)};
@@ -475,20 +626,438 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
     return finish(c, p, q, st, out, trunc_err);
 }
 
+// ---------------------------------------------------------------------------
+// Batched execution
+// ---------------------------------------------------------------------------
+
+constexpr int PANEL_SWEEPS_BATCHED = 30;
+
+struct IntSetDesc {
+    int* dst;
+    int val;
+};
+struct FillDesc {
+    void* dst;
+    int type;
+    double val;
+};
+struct GatherDesc {
+    const int* dims;
+    int L;
+    const int* status;
+    const double* norm2;
+    const double* ldelta;
+    int steps;
+    double* out;  // [error bound, discarded, norm2, status, dims[0..L]]
+};
+
+__global__ void set_ints_batched_kernel(const IntSetDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        *arr[i].dst = arr[i].val;
+}
+
+__global__ void fill_batched_kernel(const FillDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        if (arr[i].type == T_F64)
+            *(double*)arr[i].dst = arr[i].val;
+        else
+            *(float*)arr[i].dst = (float)arr[i].val;
+    }
+}
+
+// Per problem: the accumulated bound sum_i sqrt(delta_i), sum_i delta_i, the
+// centre norm, the status word and the bond dimensions, gathered in one place.
+__global__ void gather_batched_kernel(const GatherDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const GatherDesc g = arr[i];
+        double eb = 0.0, disc = 0.0;
+        for (int s = 0; s < g.steps; ++s) {
+            const double dl = g.ldelta[s] > 0.0 ? g.ldelta[s] : 0.0;
+            eb += sqrt(dl);
+            disc += dl;
+        }
+        g.out[0] = eb;
+        g.out[1] = disc;
+        g.out[2] = *g.norm2;
+        g.out[3] = (double)*g.status;
+        for (int k = 0; k <= g.L; ++k) g.out[4 + k] = (double)g.dims[k];
+    }
+}
+
+// Host staging of descriptor arrays: every batched launch reads its
+// descriptors from one device buffer uploaded before the launches.
+struct DescArena {
+    std::vector<char> host;
+    size_t add(const void* p, size_t bytes) {
+        size_t o = (host.size() + 63) / 64 * 64;
+        host.resize(o + bytes);
+        std::memcpy(host.data() + o, p, bytes);
+        return o;
+    }
+};
+
+struct Launch {
+    OpKind kind;
+    size_t off = 0;  // descriptor array offset in the device arena
+    int count = 0;
+    int cap0 = 0, cap1 = 0, cap2 = 0, prec = 0, E = 0;
+    size_t shm = 0;
+    GemmDesc gtypes{};
+    LeftMpoDesc ltypes{};
+    RightMpoDesc rtypes{};
+    bool panel = false;
+    int max_pairs = 0, max_nblk = 0, max_rows = 0;
+};
+
+struct BatchCache {
+    std::vector<const void*> key;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    char* desc_dev = nullptr;
+    size_t desc_bytes = 0;
+    size_t results_off = 0;
+    std::vector<Plan> plans;
+};
+
+static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& da, std::vector<Launch>& out) {
+    // group equal tags (phase, step, slot) across problems, in sequence order
+    std::map<std::tuple<int, int, int>, std::vector<const Op*>> groups;
+    for (const auto& seq : ops)
+        for (const Op& op : seq) groups[std::make_tuple(op.major, op.j, op.slot)].push_back(&op);
+    for (auto& kv : groups) {
+        const auto& g = kv.second;
+        const OpKind kind = g[0]->kind;
+        Launch ln;
+        ln.kind = kind;
+        ln.count = (int)g.size();
+        switch (kind) {
+            case OP_GEMM: {
+                std::vector<GemmDesc> d;
+                for (const Op* o : g) {
+                    d.push_back(o->g);
+                    ln.cap0 = std::max(ln.cap0, o->cap0);
+                    ln.cap1 = std::max(ln.cap1, o->cap1);
+                }
+                ln.gtypes = g[0]->g;
+                ln.prec = g[0]->prec;
+                ln.off = da.add(d.data(), sizeof(GemmDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_LEFT: {
+                std::vector<LeftMpoDesc> d;
+                for (const Op* o : g) {
+                    d.push_back(o->l);
+                    ln.cap0 = std::max(ln.cap0, o->cap0);
+                    ln.cap1 = std::max(ln.cap1, o->l.ny);
+                    ln.cap2 = std::max(ln.cap2, o->l.Dl * o->l.e * o->l.d * o->l.Dr);
+                }
+                ln.ltypes = g[0]->l;
+                ln.off = da.add(d.data(), sizeof(LeftMpoDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_RIGHT: {
+                std::vector<RightMpoDesc> d;
+                for (const Op* o : g) {
+                    d.push_back(o->r);
+                    ln.cap0 = std::max(ln.cap0, o->cap0);
+                    ln.cap1 = std::max(ln.cap1, o->r.nx);
+                    ln.cap2 = std::max(ln.cap2, o->r.Dl * o->r.e * o->r.d * o->r.Dr);
+                }
+                ln.rtypes = g[0]->r;
+                ln.off = da.add(d.data(), sizeof(RightMpoDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_JAC: {
+                // LDS-resident factorizations grouped by register class; the rest blocked
+                std::map<int, std::vector<JacobiDesc>> lds;
+                std::map<int, size_t> lds_shm;
+                std::vector<JacobiDesc> panel;
+                Launch pl;
+                pl.kind = OP_JAC;
+                pl.panel = true;
+                for (const Op* o : g) {
+                    if (jacobi_fits_lds(o->cap0, o->cap1)) {
+                        const int E = jacobi_lds_class(o->cap1);
+                        lds[E].push_back(o->jd);
+                        lds_shm[E] = std::max(lds_shm[E], jacobi_lds_bytes(o->cap0, o->cap1));
+                    } else {
+                        JacobiDesc d = o->jd;
+                        jacobi_panel_params(o->cap0, o->cap1, &d.bs, &d.nblk);
+                        panel.push_back(d);
+                        pl.max_pairs = std::max(pl.max_pairs, d.nblk / 2);
+                        pl.max_nblk = std::max(pl.max_nblk, d.nblk);
+                        pl.max_rows = std::max(pl.max_rows, d.basis ? std::max(o->cap0, o->cap1) : o->cap0);
+                        pl.cap1 = std::max(pl.cap1, o->cap1);
+                        pl.shm = std::max(pl.shm, sizeof(double) * 2 * (size_t)d.bs * o->cap1);
+                    }
+                }
+                for (auto& cls : lds) {
+                    Launch l2;
+                    l2.kind = OP_JAC;
+                    l2.E = cls.first;
+                    l2.shm = lds_shm[cls.first];
+                    l2.count = (int)cls.second.size();
+                    l2.off = da.add(cls.second.data(), sizeof(JacobiDesc) * cls.second.size());
+                    out.push_back(l2);
+                }
+                if (!panel.empty()) {
+                    pl.count = (int)panel.size();
+                    pl.off = da.add(panel.data(), sizeof(JacobiDesc) * panel.size());
+                    out.push_back(pl);
+                }
+                break;
+            }
+            case OP_COPY: {
+                std::vector<CopyDesc> d;
+                for (const Op* o : g) {
+                    d.push_back(o->cp);
+                    ln.cap0 = std::max(ln.cap0, o->cap0);
+                }
+                ln.off = da.add(d.data(), sizeof(CopyDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_INTCOPY: {
+                std::vector<IntCopyDesc> d;
+                for (const Op* o : g) d.push_back(o->ic);
+                ln.off = da.add(d.data(), sizeof(IntCopyDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_SETINTS: {
+                std::vector<IntSetDesc> d;
+                for (const Op* o : g)
+                    for (size_t i = 0; i < o->set_vals.size(); ++i) d.push_back(IntSetDesc{o->set_base + i, o->set_vals[i]});
+                ln.count = (int)d.size();
+                ln.off = da.add(d.data(), sizeof(IntSetDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_FILL: {
+                std::vector<FillDesc> d;
+                for (const Op* o : g) d.push_back(FillDesc{o->fill_dst, o->fill_type, o->fill_val});
+                ln.off = da.add(d.data(), sizeof(FillDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+            case OP_NORM: {
+                std::vector<NormDesc> d;
+                for (const Op* o : g) d.push_back(o->nd);
+                ln.off = da.add(d.data(), sizeof(NormDesc) * d.size());
+                out.push_back(ln);
+                break;
+            }
+        }
+    }
+}
+
+static hipError_t enqueue_launches(const std::vector<Launch>& ls, char* dev, hipStream_t s) {
+    for (const Launch& l : ls) {
+        const void* arr = dev + l.off;
+        hipError_t e = hipSuccess;
+        switch (l.kind) {
+            case OP_GEMM:
+                e = launch_gemm_batched((const GemmDesc*)arr, l.count, l.gtypes, l.cap0, l.cap1, s, l.prec);
+                break;
+            case OP_LEFT:
+                e = launch_left_mpo_batched((const LeftMpoDesc*)arr, l.count, l.ltypes, l.cap0, l.cap1, l.cap2, s);
+                break;
+            case OP_RIGHT:
+                e = launch_right_mpo_batched((const RightMpoDesc*)arr, l.count, l.rtypes, l.cap0, l.cap1, l.cap2, s);
+                break;
+            case OP_JAC:
+                if (l.panel)
+                    e = launch_jacobi_panel_batched((const JacobiDesc*)arr, l.count, l.max_pairs, l.max_nblk,
+                                                    l.max_rows, l.cap1, l.shm, PANEL_SWEEPS_BATCHED, s);
+                else
+                    e = launch_jacobi_lds_batched((const JacobiDesc*)arr, l.count, l.E, l.shm, s);
+                break;
+            case OP_COPY: e = launch_copy_batched((const CopyDesc*)arr, l.count, l.cap0, s); break;
+            case OP_INTCOPY: e = launch_copy_int_batched((const IntCopyDesc*)arr, l.count, s); break;
+            case OP_SETINTS:
+                hipLaunchKernelGGL(set_ints_batched_kernel, dim3((l.count + 255) / 256), dim3(256), 0, s,
+                                   (const IntSetDesc*)arr, l.count);
+                e = hipGetLastError();
+                break;
+            case OP_FILL:
+                hipLaunchKernelGGL(fill_batched_kernel, dim3((l.count + 255) / 256), dim3(256), 0, s,
+                                   (const FillDesc*)arr, l.count);
+                e = hipGetLastError();
+                break;
+            case OP_NORM: e = launch_norm_check_batched((const NormDesc*)arr, l.count, s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void batch_cache_free(smps_ctx* c) {
+    BatchCache* bc = (BatchCache*)c->batch;
+    if (!bc) return;
+    if (bc->exec) hipGraphExecDestroy(bc->exec);
+    if (bc->graph) hipGraphDestroy(bc->graph);
+    if (bc->desc_dev) hipFree(bc->desc_dev);
+    delete bc;
+    c->batch = nullptr;
+}
+
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                       const smps_strategy& st, smps_mps** out, double* trunc_err) {
+    if (n == 0) return SMPS_OK;
+    // ---- plans of all problems in one workspace
+    std::vector<Plan> plans(n);
+    Layout lay;
     for (int i = 0; i < n; ++i) {
-        double te = 0.0;
-        int rc = run_apply(c, U[i], v[i], st, &out[i], &te);
-        if (rc != SMPS_OK) {
+        plan_problem(plans[i], U[i], v[i], st, lay);
+        if (plans[i].max_nvec > 2048)
+            return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
+    }
+    int rc = ensure_arena(c, lay.total);
+    if (rc != SMPS_OK) return rc;
+    // cache key: the handles, their data, the workspace and the strategy
+    std::vector<const void*> key;
+    key.push_back(c->arena);
+    key.push_back((const void*)(uintptr_t)lay.total);
+    for (int i = 0; i < n; ++i) {
+        key.push_back(U[i]);
+        key.push_back(U[i]->data);
+        key.push_back(v[i]);
+        key.push_back(v[i]->data);
+    }
+    const int* sp = (const int*)&st;
+    for (size_t i = 0; i < sizeof(st) / sizeof(int); ++i) key.push_back((const void*)(uintptr_t)(unsigned)sp[i]);
+    BatchCache* bc = (BatchCache*)c->batch;
+    if (!bc || bc->key != key) {
+        batch_cache_free(c);
+        bc = new BatchCache();
+        c->batch = bc;
+        // ---- record every problem's operation sequence
+        std::vector<std::vector<Op>> ops(n);
+        for (int i = 0; i < n; ++i) {
+            Enq q{plans[i], U[i], v[i], st, c->arena, c->stream, (int*)(c->arena + plans[i].o_dims)};
+            q.rec = &ops[i];
+            hipError_t e = q.run();
+            if (e != hipSuccess) return fail(c, SMPS_EHIP, std::string("recording failed: ") + hipGetErrorString(e));
+        }
+        DescArena da;
+        std::vector<Launch> launches;
+        build_launches(ops, da, launches);
+        // gather of the per-problem results into one buffer
+        size_t stride = 0;
+        for (int i = 0; i < n; ++i) stride = std::max(stride, (size_t)(4 + plans[i].L + 1));
+        std::vector<GatherDesc> gd(n);
+        for (int i = 0; i < n; ++i) {
+            const Plan& p = plans[i];
+            gd[i] = GatherDesc{(const int*)(c->arena + p.o_dims), p.L, (const int*)(c->arena + p.o_status),
+                               (const double*)(c->arena + p.o_norm2), (const double*)(c->arena + p.o_ldelta),
+                               p.steps, nullptr};
+        }
+        const size_t gd_off = da.add(gd.data(), sizeof(GatherDesc) * n);
+        const size_t res_off = (da.host.size() + 63) / 64 * 64;
+        da.host.resize(res_off + sizeof(double) * stride * n);
+        // device copy of the descriptors (results area follows them)
+        SMPS_HIP(c, hipMalloc((void**)&bc->desc_dev, da.host.size()));
+        bc->desc_bytes = da.host.size();
+        for (int i = 0; i < n; ++i)
+            ((GatherDesc*)(da.host.data() + gd_off))[i].out = (double*)(bc->desc_dev + res_off) + stride * i;
+        SMPS_HIP(c, hipMemcpy(bc->desc_dev, da.host.data(), da.host.size(), hipMemcpyHostToDevice));
+        bc->results_off = res_off;
+        // ---- capture the whole sequence once
+        hipStream_t cs;
+        SMPS_HIP(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            e = enqueue_launches(launches, bc->desc_dev, cs);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(gather_batched_kernel, dim3((n + 255) / 256), dim3(256), 0, cs,
+                                   (const GatherDesc*)(bc->desc_dev + gd_off), n);
+                e = hipGetLastError();
+            }
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+            bc->graph = g;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&bc->exec, bc->graph, nullptr, nullptr, 0);
+        hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            batch_cache_free(c);
+            return fail(c, SMPS_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+        bc->key = key;
+        bc->plans = plans;
+    }
+    // ---- replay
+    SMPS_HIP(c, hipGraphLaunch(bc->exec, c->stream));
+    size_t stride = 0;
+    for (int i = 0; i < n; ++i) stride = std::max(stride, (size_t)(4 + plans[i].L + 1));
+    std::vector<double> res(stride * n);
+    SMPS_HIP(c, hipMemcpyAsync(res.data(), bc->desc_dev + bc->results_off, sizeof(double) * res.size(),
+                               hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < n; ++i) {
+        const int status = (int)res[stride * i + 3];
+        if (status) return fail(c, SMPS_ENUMERIC, std::string("problem ") + std::to_string(i) + ": " +
+                                                      status_message(status));
+    }
+    // ---- outputs: exact-size handles and one batched copy of every site
+    std::vector<CopyDesc> cps;
+    int cap = 0;
+    long long steps_total = 0;
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = plans[i];
+        std::vector<int> bonds(p.L + 1);
+        for (int k = 0; k <= p.L; ++k) bonds[k] = (int)res[stride * i + 4 + k];
+        bonds[0] = bonds[p.L] = 1;
+        smps_mps* m = new_mps(c, p.L, p.e, bonds);
+        if (!m) {
             for (int j = 0; j < i; ++j) {
                 smps_mps_destroy(out[j]);
                 out[j] = nullptr;
             }
-            return rc;
+            return fail(c, SMPS_ENOMEM, "output allocation failed");
         }
-        if (trunc_err) trunc_err[i] = te;
+        m->center = 0;
+        for (int k = 0; k < p.L; ++k) {
+            const double* src = k == 0 ? (p.et == T_F64 ? (const double*)(c->arena + p.o_XR[0])
+                                                        : (const double*)(c->arena + p.o_XR64))
+                                       : (const double*)(c->arena + p.o_psi[k]);
+            const int cnt = (int)m->site_size(k);
+            cps.push_back(CopyDesc{src, m->data + m->off[k], nullptr, dconst(cnt), dconst(1)});
+            cap = std::max(cap, cnt);
+        }
+        out[i] = m;
+        if (trunc_err) trunc_err[i] = res[stride * i + 0];
+        steps_total += p.steps;
     }
+    if (!cps.empty()) {
+        // descriptors of the output copies (exact sizes are only known now)
+        const size_t bytes = sizeof(CopyDesc) * cps.size();
+        int rc2 = ensure_pinned(c, bytes);
+        if (rc2 != SMPS_OK) return rc2;
+        if (c->out_desc_bytes < bytes) {
+            if (c->out_desc) hipFree(c->out_desc);
+            c->out_desc = nullptr;
+            c->out_desc_bytes = 0;
+            SMPS_HIP(c, hipMalloc((void**)&c->out_desc, bytes));
+            c->out_desc_bytes = bytes;
+        }
+        std::memcpy(c->pinned, cps.data(), bytes);
+        SMPS_HIP(c, hipMemcpyAsync(c->out_desc, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
+        SMPS_HIP(c, launch_copy_batched((const CopyDesc*)c->out_desc, (int)cps.size(), cap, c->stream));
+        SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    c->info = smps_apply_info{};
+    c->info.steps = (int)steps_total;
+    c->info.sweeps_done = st.max_sweeps;
+    c->log_delta.clear();
+    c->log_rank.clear();
+    c->log_spec.clear();
+    c->log_norm2.clear();
+    c->log_sweeps.clear();
     return SMPS_OK;
 }
 

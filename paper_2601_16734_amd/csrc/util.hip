@@ -136,3 +136,66 @@ hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipSt
 }
 
 }  // namespace smps
+
+namespace smps {
+
+__global__ __launch_bounds__(256) void copy_batched_kernel(const CopyDesc* arr) {
+    const CopyDesc d = arr[blockIdx.y];
+    const size_t n = (size_t)eval_dim(d.dims, d.a) * eval_dim(d.dims, d.b);
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) d.dst[i] = d.src[i];
+}
+
+hipError_t launch_copy_batched(const CopyDesc* arr, int count, int cap, hipStream_t s) {
+    if (count <= 0 || cap <= 0) return hipSuccess;
+    int blocks = (cap + 255) / 256;
+    if (blocks > 512) blocks = 512;
+    hipLaunchKernelGGL(copy_batched_kernel, dim3(blocks, count), dim3(256), 0, s, arr);
+    return hipGetLastError();
+}
+
+__global__ void copy_int_batched_kernel(const IntCopyDesc* arr, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        arr[i].dims[arr[i].to] = arr[i].dims[arr[i].from];
+}
+
+hipError_t launch_copy_int_batched(const IntCopyDesc* arr, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_int_batched_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    return hipGetLastError();
+}
+
+// One workgroup per descriptor: FP64 sum of squares (wavefront shuffles, then
+// LDS) and a finiteness check.
+__global__ __launch_bounds__(1024) void norm_check_batched_kernel(const NormDesc* arr) {
+    const NormDesc d = arr[blockIdx.x];
+    const int n = eval_dim(d.dims, d.n);
+    double a = 0.0;
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double x = d.x[i];
+        bad |= !isfinite(x);
+        a = fma(x, x, a);
+    }
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    __shared__ double part[16];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = a;
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += part[w];
+        *d.out = t;
+        if (s_bad) *d.status = 1;
+    }
+}
+
+hipError_t launch_norm_check_batched(const NormDesc* arr, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(norm_check_batched_kernel, dim3(count), dim3(1024), 0, s, arr);
+    return hipGetLastError();
+}
+
+}  // namespace smps

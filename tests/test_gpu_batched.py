@@ -1,0 +1,136 @@
+"""GPU parity of the batched (lockstep, graph-captured) apply + compression:
+every problem of a batch against the single-problem path and the FP64 oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mps as om
+from paper_2601_16734_amd import binding as B
+from tests.gpu_helpers import cross_fidelity_loss, rel_norm_err
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch():
+    rng = np.random.default_rng(77)
+    out = []
+    for i in range(10):
+        L = int(rng.integers(3, 13))
+        chi = int(rng.choice([2, 4, 8, 16]))
+        mps = synth.random_mps(rng, L, 2, chi)
+        kind = i % 3
+        if kind == 0:
+            mpo = synth.laplacian_mpo(L)
+        elif kind == 1:
+            mpo = synth.shift_mpo(L, 1)
+        else:
+            mpo = synth.random_mpo(rng, L, 2, int(rng.integers(1, 5)))
+        out.append(synth.Workload(f"b{i}", mps, mpo, chi, 1e-10))
+    return out
+
+
+def upload(ctx, ws):
+    vs = [ctx.mps_create(w.mps) for w in ws]
+    Us = [ctx.mpo_create(w.mpo) for w in ws]
+    return vs, Us
+
+
+def test_batched_equals_single_and_oracle(ctx):
+    ws = small_batch()
+    vs, Us = upload(ctx, ws)
+    st = B.strategy(16, 1e-10, sweeps=3)
+    outs, errs = ctx.mpo_apply_batched(Us, vs, st)
+    for i, w in enumerate(ws):
+        one, err1 = ctx.mpo_apply(Us[i], vs[i], B.strategy(w.max_bond, 1e-10, sweeps=3))
+        st_i = B.strategy(w.max_bond, 1e-10, sweeps=3)
+        got = outs[i].read()
+        single = one.read()
+        ref = om.apply_simplify(w.mpo, w.mps, 16, 1e-10, sweeps=3)
+        # the batch used max_bond 16 for all; compare with the oracle at 16
+        assert [1] + [t.shape[2] for t in got] == ref.ranks, i
+        assert rel_norm_err(ctx.norm(outs[i]), ref.norm) <= 1e-10, i
+        assert cross_fidelity_loss(got, ref.mps) <= 1e-10, i
+        assert abs(errs[i] - ref.error_bound) <= 1e-6 * ref.error_bound + 1e-12, i
+        del st_i, single
+
+
+def test_batched_matches_single_bitwise_on_lds_path(ctx):
+    ws = small_batch()
+    vs, Us = upload(ctx, ws)
+    st = B.strategy(16, 1e-10, sweeps=2)
+    outs, errs = ctx.mpo_apply_batched(Us, vs, st)
+    for i in range(len(ws)):
+        one, err1 = ctx.mpo_apply(Us[i], vs[i], st)
+        a, b = outs[i].read(), one.read()
+        assert [t.shape for t in a] == [t.shape for t in b]
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+        assert errs[i] == err1
+
+
+def test_batched_graph_replay_is_deterministic(ctx):
+    ws = small_batch()
+    vs, Us = upload(ctx, ws)
+    st = B.strategy(16, 1e-10, sweeps=2)
+    first, e1 = ctx.mpo_apply_batched(Us, vs, st)
+    a = [o.read() for o in first]
+    for _ in range(2):
+        again, e2 = ctx.mpo_apply_batched(Us, vs, st)
+        assert e1 == e2
+        for x, o in zip(a, again):
+            for s1, s2 in zip(x, o.read()):
+                np.testing.assert_array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_batched_mixed_precision_vs_oracle(ctx, precision):
+    ws = small_batch()
+    vs, Us = upload(ctx, ws)
+    outs, errs = ctx.mpo_apply_batched(Us, vs, B.strategy(16, 1e-10, sweeps=3, precision=precision))
+    for i, w in enumerate(ws):
+        ref = om.apply_simplify(w.mpo, w.mps, 16, 1e-10, sweeps=3)
+        got = outs[i].read()
+        assert rel_norm_err(ctx.norm(outs[i]), ref.norm) <= 1e-8, (precision, i)
+        assert cross_fidelity_loss(got, ref.mps) <= 1e-8, (precision, i)
+
+
+@pytest.fixture(scope="module")
+def qtt_sample():
+    """The first 16 problems of the 512-problem QTT batch (n in [8, 30], chi in
+    {4, ..., 128}, FP32 inputs, Laplacian or shift), including a chi = 128
+    chain whose two-site tensors exceed the LDS and take the blocked path."""
+    return synth.workload_batch(count=16)
+
+
+def test_qtt_batch_sample_vs_oracle(ctx, qtt_sample):
+    ws = qtt_sample
+    vs = [ctx.mps_create(w.mps, dtype=np.float32) for w in ws]
+    Us = [ctx.mpo_create(w.mpo) for w in ws]
+    # each problem keeps its own chi as the bond cap: batch problems by cap
+    by_cap = {}
+    for i, w in enumerate(ws):
+        by_cap.setdefault(w.max_bond, []).append(i)
+    for cap, idx in sorted(by_cap.items()):
+        outs, errs = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], B.strategy(cap, 1e-10))
+        for o, i in zip(outs, idx):
+            w = ws[i]
+            mps64 = [t.astype(np.float64) for t in w.mps]
+            ref = om.apply_simplify(w.mpo, mps64, cap, 1e-10, sweeps=4)
+            got = o.read()
+            ne, fl = rel_norm_err(ctx.norm(o), ref.norm), cross_fidelity_loss(got, ref.mps)
+            print(f"problem {i} n={w.meta['n']} chi={cap}: norm err {ne:.2e} fidelity loss {fl:.2e}")
+            assert ne <= 1e-8 and fl <= 1e-8, i
+
+
+def test_single_blocked_path_vs_oracle(ctx, qtt_sample):
+    w = [x for x in qtt_sample if x.meta["chi"] == 128][0]
+    v = ctx.mps_create(w.mps, dtype=np.float32)
+    U = ctx.mpo_create(w.mpo)
+    out, err = ctx.mpo_apply(U, v, B.strategy(128, 1e-10))
+    ref = om.apply_simplify(w.mpo, [t.astype(np.float64) for t in w.mps], 128, 1e-10, sweeps=4)
+    got = out.read()
+    assert rel_norm_err(ctx.last_info()["norm"], ref.norm) <= 1e-8
+    assert cross_fidelity_loss(got, ref.mps) <= 1e-8
