@@ -90,6 +90,7 @@ struct JacobiDesc {
     double* fro2;        // blocked path: ||X||_F^2 (device scalar, filled by the launcher)
     double* basis;       // len x len: all normalised vectors when they span R^len, else the
                          // identity; pre-rotates the next factorization at this bond (nullable)
+    double floor_eps;    // unit roundoff used by the numerical rank floor (FP64: 2^-52)
     int bs, nblk;        // blocked path: vectors per block, number of blocks (even)
     int* done;           // blocked path, batched: set once a sweep rotated nothing
 };

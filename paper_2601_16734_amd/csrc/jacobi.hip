@@ -42,10 +42,11 @@ __device__ __forceinline__ int tourney(int pos, int rd, int n2) {
 }
 
 // Numerical rank floor: a vector whose norm is at most
-// eps * max(nvec, len) * ||X||_F is rounding noise of a rank-deficient matrix;
-// it takes part in no rotation and counts as a zero singular value.
-__device__ __forceinline__ double zero_floor2(double total2, int nv, int len) {
-    const double f = DBL_EPSILON * (double)(nv > len ? nv : len);
+// u * max(nvec, len) * ||X||_F, with u the unit roundoff of the arithmetic that
+// produced X, is rounding noise of a rank-deficient matrix; it takes part in
+// no rotation and counts as a zero singular value.
+__device__ __forceinline__ double zero_floor2(double total2, int nv, int len, double u) {
+    const double f = u * (double)(nv > len ? nv : len);
     return f * f * total2;
 }
 
@@ -77,13 +78,13 @@ __device__ __forceinline__ double row_sum16(double x) {
 // the dot product and the rotation (len <= 16 E); E = 0: generic strided loop.
 // Returns (block-uniform) the number of sweeps that applied a rotation.
 template <int E>
-__device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double total2,
+__device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double floor2,
                              int true_len, int max_sweeps = JAC_MAX_SWEEPS) {
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
     // cosine threshold: rounding in a length-n dot product is ~eps*sqrt(n); eps*n leaves margin
     const double tol = DBL_EPSILON * (double)(true_len > 16 ? true_len : 16);
-    const double tiny = fmax(DBL_MIN * 1.0e4, zero_floor2(total2, nv, true_len));
+    const double tiny = fmax(DBL_MIN * 1.0e4, floor2);
     const int P = (nv + 1) / 2, n2 = 2 * P;
     constexpr int g = 16;
     const int gl = tid & (g - 1), gi = tid / g, ngroups = JT / g;
@@ -206,7 +207,7 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
     if (tid == 0) {
         double t2 = 0.0;
         for (int j = 0; j < nv; ++j) t2 += sig_raw[j];
-        s_floor2 = zero_floor2(t2, nv, len);
+        s_floor2 = zero_floor2(t2, nv, len, d.floor_eps);
     }
     __syncthreads();
     for (int j = tid; j < nv; j += JT) sig_raw[j] = sig_raw[j] > s_floor2 ? sqrt(sig_raw[j]) : 0.0;
@@ -352,7 +353,8 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
         }
         __syncthreads();
     }
-    const int nsw = jacobi_orth_t<E>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag, s_total2, len);
+    const int nsw = jacobi_orth_t<E>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag,
+                                      zero_floor2(s_total2, nv, len, d.floor_eps), len);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
     jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis);
@@ -398,7 +400,8 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const J
         return;
     }
     // one inner sweep per round: the outer tournament then acts as one cyclic ordering
-    const bool any = jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, *d.fro2, len, 1) > 0;
+    const bool any =
+        jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
     if (!any) return;
     for (size_t e = tid; e < (size_t)nloc * len; e += JT) {
         const int j = (int)(e / len), l = (int)(e % len);
@@ -417,6 +420,7 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const 
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     jacobi_select(d.X, nv, len, len, sig_raw, sig_sorted, perm_s, d, &s_delta);
+    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // blocked sweeps are not counted per step
     for (int j = threadIdx.x; j < nv; j += JT) d.perm[j] = perm_s[j];
 }
 

@@ -365,6 +365,7 @@ struct Enq {
         d.fro2 = at<double>(p.o_fro2);
         d.conv = at<int>(p.o_flag);
         d.done = at<int>(p.o_done);
+        d.floor_eps = 2.220446049250313e-16;
         if (step >= 0) {
             d.log_delta = at<double>(p.o_ldelta) + step;
             d.log_rank = at<int>(p.o_lrank) + step;
@@ -630,7 +631,7 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
 // Batched execution
 // ---------------------------------------------------------------------------
 
-constexpr int PANEL_SWEEPS_BATCHED = 30;
+constexpr int PANEL_SWEEPS_BATCHED = 40;
 
 struct IntSetDesc {
     int* dst;
