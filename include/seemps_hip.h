@@ -186,7 +186,7 @@ int smps_norm(smps_ctx *ctx, const smps_mps *a, double *out);
  *       *final_loss receives the mean loss of the last epoch.
  *   smps_rank_mlp_predict: out[n] = predicted log rank.
  *   smps_rank_mlp_get / set: the FP32 master parameters in the order
- *       W1[64x32], b1[64], W2[64x64], b2[64], W3[1x64], b3[1] (4353 floats). */
+ *       W1[64x32], b1[64], W2[64x64], b2[64], W3[1x64], b3[1] (6337 floats). */
 int smps_rank_mlp_init(smps_ctx *ctx, unsigned long long seed);
 int smps_rank_mlp_train(smps_ctx *ctx, int n, const float *feats, const float *labels, int epochs, int batch,
                         float lr, float *final_loss);

@@ -310,3 +310,19 @@ def workload_decaying(rep: int = 0, L: int = 64, chi: int = 512, D: int = 8) -> 
     mps, taus = decaying_spectrum_mps(rng, L, 2, chi)
     mpo = random_mpo(rng, L, 2, D)
     return Workload(f"decaying_L{L}_chi{chi}_D{D}", mps, mpo, chi, 1e-10, meta={"taus": taus})
+
+
+# ---- rank-predictor inputs -------------------------------------------------------
+def mlp_params(rng: np.random.Generator, n: int = 6337, scale: float = 0.2) -> np.ndarray:
+    """Random FP32 parameter vector for the 32-64-64-1 rank predictor."""
+    return (rng.standard_normal(n) * scale).astype(np.float32)
+
+
+def mlp_inputs(rng: np.random.Generator, n: int, floor: float = 1e-30):
+    """n synthetic log-spectrum feature rows (32 descending values starting at
+    0, floored at log(floor)) and log-rank labels in [0, log 512]."""
+    steps = rng.exponential(rng.uniform(0.05, 2.0, size=(n, 1)), size=(n, 32))
+    steps[:, 0] = 0.0
+    X = np.maximum(-np.cumsum(steps, axis=1), math.log(floor)).astype(np.float32)
+    y = rng.uniform(0.0, math.log(512.0), size=n).astype(np.float32)
+    return X, y

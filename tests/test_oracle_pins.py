@@ -288,3 +288,60 @@ def test_tt_svd_reference_quality():
     assert lb * (1 - 1e-10) <= var_err
     # the variational optimum is never worse than twice the quasi-optimal TT-SVD error here
     assert var_err <= 2 * tt_err
+
+
+# ---------------------------------------------------------------- rank-predictor network (oracle side)
+
+def test_bf16_rounding_hand_values():
+    from oracle import mlp
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.1], dtype=np.float32)
+    r = mlp.bf16_round(x)
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: even mantissa wins (1); 1 + 3*2^-8 rounds up to 1 + 2^-6
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0 + 2.0 ** -6) and r[3] == -2.5
+    assert abs(r[4] - 0.1) < 0.1 * 2.0 ** -8 and (r.view(np.uint32) & 0xFFFF == 0).all()
+
+
+def test_mlp_backward_matches_finite_differences():
+    from oracle import mlp
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(mlp.N_PARAMS) * 0.2
+    X = rng.standard_normal((6, 32))
+    y = rng.standard_normal(6) * 2
+    L, g = mlp.loss_and_grad(p, X, y, quantize=False)
+    h = 1e-6
+    idx = rng.choice(mlp.N_PARAMS, 60, replace=False)
+    idx = np.concatenate([idx, [mlp.N_PARAMS - 1, 2048, 2048 + 64 + 4095]])
+    for i in idx:
+        e = np.zeros(mlp.N_PARAMS)
+        e[i] = h
+        fd = (mlp.loss_and_grad(p + e, X, y, quantize=False)[0] - mlp.loss_and_grad(p - e, X, y, quantize=False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), i
+
+
+def test_mlp_loss_asymmetry_and_features():
+    from oracle import mlp
+    p = np.zeros(mlp.N_PARAMS)
+    X = np.zeros((2, 32))
+    # output is b3 = 0: label 0.5 -> under-prediction (x4), label -0.5 -> over-prediction
+    Lu, _ = mlp.loss_and_grad(p, X[:1], [0.5])
+    Lo, _ = mlp.loss_and_grad(p, X[:1], [-0.5])
+    assert abs(Lu - 4 * 0.125) < 1e-15 and abs(Lo - 0.125) < 1e-15
+    L3, _ = mlp.loss_and_grad(p, X[:1], [3.0])
+    assert abs(L3 - 4 * 2.5) < 1e-15  # linear branch beyond the Huber threshold
+    f = mlp.features([2.0, 1.0, 0.0])
+    assert f[0] == 0.0 and abs(f[1] - np.log(0.5)) < 1e-15 and f[2] == np.log(1e-30) and f[31] == np.log(1e-30)
+
+
+def test_adam_constant_gradient_moves_by_lr_per_step():
+    """With a constant gradient the bias-corrected moments equal g and g^2 at
+    every step, so Adam moves each coordinate by lr * g / (|g| + eps)."""
+    from oracle.mlp import adam_step
+    g = np.array([1.0, -2.0, 0.0, 1e-3])
+    p = np.array([0.5, 0.5, 0.5, 0.5])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lr = 1e-2
+    for t in range(1, 6):
+        p_new, m, v = adam_step(p, g, m, v, t, lr)
+        np.testing.assert_allclose(p - p_new, lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+        p = p_new
