@@ -83,6 +83,9 @@ struct ApplyProblem {
 int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
               double* trunc_err);
 void mlp_free(smps_ctx* c);
+// rank predictor: log-rank predictions for n device feature rows (32 floats each)
+hipError_t mlp_predict_device(smps_ctx* c, const float* feats_dev, int n, float* out_dev, hipStream_t s);
+bool mlp_ready(const smps_ctx* c);
 void batch_cache_free(smps_ctx* c);
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                       const smps_strategy& st, smps_mps** out, double* trunc_err);
