@@ -65,8 +65,21 @@ enum {
 /* factorization of the two-site tensor */
 enum {
     SMPS_FACT_SVD = 0,        /* exact one-sided Jacobi SVD */
-    SMPS_FACT_RSVD_MLP = 1    /* randomized SVD sized by the rank predictor, exact SVD as fallback */
+    SMPS_FACT_RSVD_MLP = 1,   /* randomized SVD sized by the rank predictor, exact SVD as fallback */
+    SMPS_FACT_RSVD_PREV = 2   /* randomized SVD sized by the bond's previous kept rank, exact fallback */
 };
+/* Randomized factorization (single-problem path only): range finder with one
+   subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4) on a Gaussian
+   sketch of k = r + 16 rows drawn from Philox4x64-10 (counter (block, step, 0, 0)),
+   orthonormalised by the Jacobi kernel, then the SVD of the small projected
+   matrix.  r is the predicted rank: ceil(exp(output)) of the rank predictor on
+   the bond's previous spectrum (RSVD_MLP), or the bond's previous kept rank
+   (RSVD_PREV).  The step is exact when r >= min(max_bond, m, n) (a rank at the
+   cap cannot meet the tolerance) or k >= min(m, n).  The discarded weight
+   ||theta||^2 - sum_{j<r} s_j^2 is exact; the step is accepted when it is at
+   most tol * ||theta||^2 (relative-norm rule) and r <= k - 8, else the exact
+   SVD replaces it.  The first left-to-right pass is always exact (no previous
+   spectrum to predict from). */
 
 /* Compression strategy (Sec. 2.3): maximum bond, tolerance, rule, and the
    number of sweeps of the variational search. */
@@ -76,7 +89,8 @@ typedef struct {
     int trunc_mode;    /* SMPS_TRUNC_* */
     int max_sweeps;    /* >= 1; a sweep is a left-to-right and a right-to-left pass */
     double sweep_tol;  /* 0: always run max_sweeps; > 0: stop once the relative change of
-                          ||psi||^2 over a sweep falls below it (one host sync per sweep) */
+                          ||psi||^2 over a sweep falls below it (one host sync per sweep;
+                          the batched entry point always runs max_sweeps) */
     int precision;     /* SMPS_PREC_* */
     int factorization; /* SMPS_FACT_* */
 } smps_strategy;
@@ -159,6 +173,11 @@ int smps_last_info(const smps_ctx *ctx, smps_apply_info *info);
    number of steps available. */
 int smps_last_log(const smps_ctx *ctx, int max_steps, double *deltas, int *ranks, double *spectra,
                   int *steps);
+/* Factorization used at each step of the last single-problem apply/simplify:
+   0 exact SVD, +k randomized with sketch k accepted, -k randomized with sketch k
+   rejected and replaced by the exact SVD.  max_steps bounds the copy; *steps
+   receives the number of steps available. */
+int smps_last_factor_log(const smps_ctx *ctx, int max_steps, int *kinds, int *steps);
 
 /* Batched apply: n independent (U[i], v[i]) problems of arbitrary length and
    bonds under one strategy, advanced together bond step by bond step; the

@@ -197,7 +197,7 @@ def _split(theta, a, s, t, c, tol, max_bond, mode, direction):
 
 
 def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
-                   mode: int = REL_NORM2, guess=None) -> SweepResult:
+                   mode: int = REL_NORM2, guess=None, split_hook=None) -> SweepResult:
     """Route F: compress U v with three-layer environments <psi | U | v>.
 
     L[k][a, b, x] contracts sites < k of psi (a), U (b) and v (x);
@@ -207,6 +207,11 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
         theta[a,s,t,c] = sum L[k][a,b,x] A_k[x,p,y] B_k[b,s,p,b']
                              A_{k+1}[y,q,z] B_{k+1}[b',t,q,b''] R[k+2][c,b'',z],
     which is split by a truncated SVD and the centre moved on.
+
+    split_hook (optional) may replace the exact split of a step: it is called
+    as split_hook(theta, bond, direction, sweep, step, previous) with previous
+    = (spectrum, kept rank) of the bond's last split, or None, and returns
+    None (exact split) or (left, right, r, delta, s).
     """
     L = len(mps)
     A = [np.asarray(x, dtype=np.float64) for x in mps]
@@ -239,12 +244,21 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
         return chain("abx,xpy,bspe,yqz,etqf,cfz->astc",
                      Lenv[k], A[k], B[k], A[k + 1], B[k + 1], Renv[k + 2])
 
+    last_spectrum = {}
+    step = 0
     for sw in range(sweeps):
         for direction, bonds in ((+1, range(0, L - 1)), (-1, range(L - 2, -1, -1))):
             for k in bonds:
                 th = theta_at(k)
                 a, s, t, c = th.shape
-                left, right, r, delta, S = _split(th, a, s, t, c, tol, max_bond, mode, direction)
+                got = None
+                if split_hook is not None:
+                    got = split_hook(th, k, direction, sw, step, last_spectrum.get(k))
+                if got is None:
+                    got = _split(th, a, s, t, c, tol, max_bond, mode, direction)
+                left, right, r, delta, S = got
+                last_spectrum[k] = (S, r)
+                step += 1
                 psi[k], psi[k + 1] = left, right
                 res.deltas.append(delta)
                 res.norms2.append(float(np.sum(S[:r] ** 2)))

@@ -21,7 +21,7 @@ F64, F32 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "bf16": PREC_BF16}
 TRUNC_REL_NORM2, TRUNC_REL_SV = 0, 1
-FACT_SVD, FACT_RSVD_MLP = 0, 1
+FACT_SVD, FACT_RSVD_MLP, FACT_RSVD_PREV = 0, 1, 2
 MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
 
 # every symbol the header declares, in declaration order
@@ -30,7 +30,7 @@ EXPORTS = [
     "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
-    "smps_last_info", "smps_last_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad",
 ]
@@ -85,6 +85,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_simplify": (c_int, [vp, vp, POINTER(Strategy), POINTER(vp), dp]),
         "smps_last_info": (c_int, [vp, POINTER(ApplyInfo)]),
         "smps_last_log": (c_int, [vp, c_int, dp, ip, dp, ip]),
+        "smps_last_factor_log": (c_int, [vp, c_int, ip, ip]),
         "smps_mpo_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
         "smps_scprod": (c_int, [vp, vp, vp, dp]),
         "smps_norm": (c_int, [vp, vp, dp]),
@@ -290,6 +291,13 @@ class Context:
                                            ranks.ctypes.data_as(POINTER(c_int)),
                                            spec.ctypes.data_as(POINTER(c_double)), byref(n)))
         return deltas, ranks, spec
+
+    def last_factor_log(self) -> np.ndarray:
+        n = c_int()
+        self._check(self.lib.smps_last_factor_log(self.h, 0, None, byref(n)))
+        kinds = np.zeros(n.value, dtype=np.int32)
+        self._check(self.lib.smps_last_factor_log(self.h, n.value, kinds.ctypes.data_as(POINTER(c_int)), byref(n)))
+        return kinds
 
     def set_profiling(self, on: bool):
         self._check(self.lib.smps_ctx_set_profiling(self.h, 1 if on else 0))

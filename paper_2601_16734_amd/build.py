@@ -19,8 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libseemps_hip.so")
 
-SOURCES = ["gemm.hip", "mpo_kernels.hip", "jacobi.hip", "util.hip", "sweep.hip", "abi.hip", "mlp.hip",
-           "batched.hip"]
+SOURCES = ["gemm.hip", "mpo_kernels.hip", "jacobi.hip", "util.hip", "sweep.hip", "abi.hip", "mlp.hip", "rsvd.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]
@@ -44,7 +43,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

@@ -120,7 +120,8 @@ static int check_strategy(smps_ctx* c, const smps_strategy* st) {
         return fail(c, SMPS_EINVAL, "unknown truncation mode");
     if (st->precision < SMPS_PREC_FP64 || st->precision > SMPS_PREC_BF16)
         return fail(c, SMPS_EINVAL, "unknown precision");
-    if (st->factorization != SMPS_FACT_SVD && st->factorization != SMPS_FACT_RSVD_MLP)
+    if (st->factorization != SMPS_FACT_SVD && st->factorization != SMPS_FACT_RSVD_MLP &&
+        st->factorization != SMPS_FACT_RSVD_PREV)
         return fail(c, SMPS_EINVAL, "unknown factorization");
     return SMPS_OK;
 }
@@ -428,6 +429,15 @@ int smps_last_log(const smps_ctx* c, int max_steps, double* deltas, int* ranks, 
     if (deltas) std::memcpy(deltas, c->log_delta.data(), sizeof(double) * m);
     if (ranks) std::memcpy(ranks, c->log_rank.data(), sizeof(int) * m);
     if (spectra) std::memcpy(spectra, c->log_spec.data(), sizeof(double) * 32 * (size_t)m);
+    return SMPS_OK;
+}
+
+int smps_last_factor_log(const smps_ctx* c, int max_steps, int* kinds, int* steps) {
+    if (!c) return SMPS_EINVAL;
+    const int n = (int)c->log_fact.size();
+    if (steps) *steps = n;
+    const int m = std::min(n, std::max(0, max_steps));
+    if (kinds && m > 0) std::memcpy(kinds, c->log_fact.data(), sizeof(int) * m);
     return SMPS_OK;
 }
 

@@ -93,6 +93,10 @@ struct JacobiDesc {
     double floor_eps;    // unit roundoff used by the numerical rank floor (FP64: 2^-52)
     int bs, nblk;        // blocked path: vectors per block, number of blocks (even)
     int* done;           // blocked path, batched: set once a sweep rotated nothing
+    int gram;            // X is a symmetric PSD Gram matrix B B^T: a converged row has norm
+                         // s_j^2, so s_j = sqrt(row norm) and Q rows are divided by s_j^2
+    const double* total_ext;  // nullable: exact total weight ||B||_F^2; the weight that the
+                              // computed s_j miss is then counted in every tail
 };
 
 }  // namespace smps
@@ -157,4 +161,11 @@ hipError_t launch_sumsq(const double* x, const int* dims, DimExpr n, int n_cap, 
 hipError_t launch_check_finite(const double* x, const int* dims, DimExpr n, int n_cap, int* status,
                                hipStream_t s);
 hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipStream_t s);
+// randomized factorization pieces (rsvd.hip)
+hipError_t launch_sketch(double* G, int rows, int nvec, unsigned long long step, hipStream_t s);
+hipError_t launch_rank_features(const double* lspec, int first, int stride, int count, float* feats, hipStream_t s);
+hipError_t launch_rsvd_accept(const int* dims, int rank_idx, const double* delta, const double* total, int ksketch,
+                              int oversample, double tol, int mode, const int* status, int* flag, hipStream_t s);
+hipError_t launch_identity(double* B, const int* dims, DimExpr n, int cap, hipStream_t s);
+constexpr int RSVD_OVERSAMPLE = 16;
 }  // namespace smps

@@ -210,7 +210,10 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
         s_floor2 = zero_floor2(t2, nv, len, d.floor_eps);
     }
     __syncthreads();
-    for (int j = tid; j < nv; j += JT) sig_raw[j] = sig_raw[j] > s_floor2 ? sqrt(sig_raw[j]) : 0.0;
+    for (int j = tid; j < nv; j += JT) {
+        const double a = sig_raw[j];
+        sig_raw[j] = a > s_floor2 ? (d.gram ? sqrt(sqrt(a)) : sqrt(a)) : 0.0;
+    }
     __syncthreads();
     // descending order with ties broken by index
     for (int j = tid; j < nv; j += JT) {
@@ -226,43 +229,42 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
     __syncthreads();
     __shared__ int s_r;
     if (tid == 0) {
+        // weight not represented by the computed values (zero unless an exact
+        // total is supplied), counted in every tail
+        double all = 0.0;
+        for (int j = nv - 1; j >= 0; --j) all += sig_sorted[j] * sig_sorted[j];
+        const double total = d.total_ext ? *d.total_ext : all;
+        const double missed = d.total_ext ? fmax(0.0, total - all) : 0.0;
         int r;
-        double delta;
         if (d.mode == SMPS_TRUNC_REL_SV) {
             r = 0;
             const double thr = d.tol * sig_sorted[0];
             for (int j = 0; j < nv; ++j) r += sig_sorted[j] > thr;
-            if (r < 1) r = 1;
-            if (r > d.max_rank) r = d.max_rank;
-            if (r > nv) r = nv;
-            if (r > len) r = len;
-            delta = 0.0;
-            for (int j = nv - 1; j >= r; --j) delta += sig_sorted[j] * sig_sorted[j];
         } else {
-            // t[j] = sum_{i>=j} s_i^2 accumulated from the smallest value upwards
-            double total = 0.0;
-            for (int j = nv - 1; j >= 0; --j) total += sig_sorted[j] * sig_sorted[j];
+            // smallest r >= 1 whose tail (summed from the smallest value up) fits
             const double thr = d.tol * total;
-            // smallest r >= 1 with t[r] <= thr: scan the tail upwards
-            double t = 0.0;
-            r = nv;
+            double t = missed;
             int cand = nv;
-            // t at cand = nv is 0 (<= thr always); walk down while the tail still fits
-            while (cand > 1) {
-                const double tn = t + sig_sorted[cand - 1] * sig_sorted[cand - 1];
-                if (tn <= thr) {
-                    t = tn;
-                    --cand;
-                } else {
-                    break;
+            if (t <= thr) {
+                while (cand > 1) {
+                    const double tn = t + sig_sorted[cand - 1] * sig_sorted[cand - 1];
+                    if (tn <= thr) {
+                        t = tn;
+                        --cand;
+                    } else {
+                        break;
+                    }
                 }
             }
             r = cand;
-            if (r > d.max_rank) r = d.max_rank;
-            if (r > len) r = len;
-            delta = 0.0;
-            for (int j = nv - 1; j >= r; --j) delta += sig_sorted[j] * sig_sorted[j];
         }
+        if (r < 1) r = 1;
+        if (r > d.max_rank) r = d.max_rank;
+        if (r > nv) r = nv;
+        if (r > len) r = len;
+        double delta = 0.0;
+        for (int j = nv - 1; j >= r; --j) delta += sig_sorted[j] * sig_sorted[j];
+        delta += missed;
         s_r = r;
         *s_delta = delta;
         if (d.log_delta) *d.log_delta = delta;
@@ -286,10 +288,10 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
 // Kept rows: Q[i] = W[perm[i]] / s_i (a zero vector only occurs when the
 // whole matrix is zero and one row is kept: it becomes the first unit vector).
 __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, const double* sig_sorted,
-                                  const int* perm, int r, double* Q, double* basis) {
+                                  const int* perm, int r, double* Q, double* basis, int gram) {
     for (size_t e = threadIdx.x; e < (size_t)r * len; e += JT) {
         const int i = (int)(e / len), l = (int)(e % len);
-        const double s = sig_sorted[i];
+        const double s = gram ? sig_sorted[i] * sig_sorted[i] : sig_sorted[i];
         Q[e] = s > 0.0 ? W[(size_t)perm[i] * ld + l] / s : (l == i ? 1.0 : 0.0);
     }
     if (!basis) return;
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
                                       zero_floor2(s_total2, nv, len, d.floor_eps), len);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
-    jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis);
+    jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram);
 }
 
 // One round of the blocked path: workgroup i takes the block pair of
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d0, const 
     const int r = d.dims_out[d.rank_idx];
     const int i = blockIdx.y;
     if (i < r) {
-        const double s = d.sigma[i];
+        const double s = d.gram ? d.sigma[i] * d.sigma[i] : d.sigma[i];
         const double* w = d.X + (size_t)d.perm[i] * len;
         for (int l = blockIdx.x * 256 + threadIdx.x; l < len; l += gridDim.x * 256)
             d.Q[(size_t)i * len + l] = s > 0.0 ? w[l] / s : (l == i ? 1.0 : 0.0);

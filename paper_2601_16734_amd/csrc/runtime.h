@@ -23,6 +23,9 @@ struct smps_ctx {
     smps_apply_info info{};
     std::vector<double> log_delta, log_spec, log_norm2;
     std::vector<int> log_rank, log_sweeps;
+    // per step: 0 exact factorization, +k randomized with sketch k accepted,
+    // -k randomized with sketch k replaced by the exact one
+    std::vector<int> log_fact;
     // rank predictor state (device buffers, see mlp.hip)
     void* mlp = nullptr;
     // batched execution: captured graph of the last batch shape, and the

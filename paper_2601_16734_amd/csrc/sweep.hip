@@ -62,6 +62,10 @@ struct Plan {
     size_t o_tmp, o_theta, o_theta2, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
     size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
     size_t o_R64a, o_R64b, o_XR64, o_Y64;
+    // randomized factorization scratch (allocated only when it is requested)
+    int fact = SMPS_FACT_SVD;
+    size_t o_rs_G = 0, o_rs_Y = 0, o_rs_P = 0, o_rs_T = 0, o_rs_C = 0, o_rs_W = 0, o_rs_Q = 0;
+    size_t o_rs_tot = 0, o_rs_flag = 0, o_rs_feat = 0, o_rs_pred = 0;
     int steps = 0;
     size_t max_theta = 0, max_tmp = 0, max_env = 0, max_xr = 0;
     int max_nvec = 0;
@@ -99,7 +103,8 @@ void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_stra
     const auto& c = p.capb;
     const auto& Dm = p.Dm;
     const auto& cv = p.chiv;
-    p.o_dims = lay.add(sizeof(int) * (L + 2));
+    // bonds 0..L, a scratch rank slot (L + 1) and two for the randomized path
+    p.o_dims = lay.add(sizeof(int) * (L + 4));
     p.o_status = lay.add(sizeof(int));
     p.o_flag = lay.add(sizeof(int));
     p.o_norm2 = lay.add(sizeof(double));
@@ -167,6 +172,16 @@ void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_stra
         for (int k = 0; k < L; ++k) ymax = std::max(ymax, (size_t)cv[k] * p.dv[k] * c[k + 1] * Dm[k + 1]);
         p.o_Y64 = lay.add(8 * ymax);
     }
+    p.fact = st.factorization;
+    if (p.fact != SMPS_FACT_SVD) {
+        // a sketch k < min(nvec, len) keeps every buffer below the two-site size
+        for (size_t* o : {&p.o_rs_G, &p.o_rs_Y, &p.o_rs_P, &p.o_rs_T, &p.o_rs_C, &p.o_rs_W, &p.o_rs_Q})
+            *o = lay.add(8 * p.max_theta);
+        p.o_rs_tot = lay.add(sizeof(double));
+        p.o_rs_flag = lay.add(sizeof(int));
+        p.o_rs_feat = lay.add(sizeof(float) * 32 * (size_t)std::max(1, L));
+        p.o_rs_pred = lay.add(sizeof(float) * (size_t)std::max(1, L));
+    }
 }
 
 
@@ -210,6 +225,13 @@ struct Enq {
     std::vector<Op>* rec = nullptr;  // record instead of launching
     mutable const char* where = "";
     mutable int cur_major = 0, cur_j = 0, cur_slot = 0;
+    // single path only: sweeps and steps actually run (early stop on sweep_tol),
+    // the factorization log and the predicted log ranks of the current half-sweep
+    mutable int sweeps_done = 0, steps_done = 0;
+    mutable std::vector<int> fact_log;
+    mutable std::vector<float> preds;
+    mutable std::vector<int> prev_rank;
+    mutable std::vector<int> hdims;
 
     template <typename T = void>
     T* at(size_t off) const { return (T*)(base + off); }
@@ -385,6 +407,148 @@ struct Enq {
         return emit(std::move(op));
     }
 
+    hipError_t read_dims() const {
+        hdims.assign(p.L + 4, 0);
+        hipError_t e = hipMemcpyAsync(hdims.data(), dims, sizeof(int) * (p.L + 4), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+
+    // Predicted rank of every bond for the coming half-sweep (as log r), from
+    // the step first + stride * k that last factorized bond k: the rank
+    // predictor applied to that step's spectrum, or that step's kept rank.
+    hipError_t predict_ranks(int first, int stride) const {
+        const int nb = p.L - 1;
+        preds.assign(nb, 0.f);
+        if (p.fact == SMPS_FACT_RSVD_PREV) {
+            std::vector<int> r(nb);
+            const int lo = std::min(first, first + stride * (nb - 1));
+            hipError_t e = hipMemcpyAsync(r.data(), at<int>(p.o_lrank) + lo, sizeof(int) * nb,
+                                          hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return e;
+            prev_rank.assign(nb, 1);
+            for (int k = 0; k < nb; ++k) prev_rank[k] = r[first + stride * k - lo];
+            return hipSuccess;
+        }
+        float* feats = at<float>(p.o_rs_feat);
+        float* pr = at<float>(p.o_rs_pred);
+        hipError_t e = launch_rank_features(at<double>(p.o_lspec), first, stride, nb, feats, s);
+        if (e != hipSuccess) return e;
+        e = mlp_predict_device(ctx, feats, nb, pr, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(preds.data(), pr, sizeof(float) * nb, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+
+    // Sketch size for bond k at a step whose matrix is nv x ln; 0 means the
+    // exact SVD (predicted rank at the cap, where the randomized step could
+    // not meet the tolerance, or a sketch as large as the matrix).
+    int sketch_size(int k, int nv, int ln) const {
+        const int lim = std::min(std::min(nv, ln), st.max_bond);
+        int rhat;
+        if (p.fact == SMPS_FACT_RSVD_PREV) {
+            rhat = std::min(lim, prev_rank[k]);
+        } else {
+            const double lr = std::min(30.0, std::max(0.0, (double)preds[k]));
+            rhat = (int)std::min<double>(lim, std::ceil(std::exp(lr)));
+        }
+        rhat = std::max(1, rhat);
+        if (rhat >= lim) return 0;
+        const int ks = rhat + RSVD_OVERSAMPLE;
+        return ks < std::min(nv, ln) ? ks : 0;
+    }
+
+    // Randomized factorization of the rows of X (nv x ln, live sizes known on
+    // the host) with sketch ks; on acceptance the kept rows go to dest, the
+    // rank to dims[bond + 1], the log entries of `step` are written and the
+    // warm-start basis of the bond becomes the identity.  *ok reports acceptance.
+    hipError_t rsvd(const double* X, int nv, int ln, int ks, int step, int bond, int mr, double* dest,
+                    double* basis, bool* ok) const {
+        const int KS1 = p.L + 2, KS2 = p.L + 3;
+        double* G = at<double>(p.o_rs_G);
+        double* Y = at<double>(p.o_rs_Y);
+        double* P = at<double>(p.o_rs_P);
+        double* T = at<double>(p.o_rs_T);
+        double* C = at<double>(p.o_rs_C);
+        double* W = at<double>(p.o_rs_W);
+        double* Qr = at<double>(p.o_rs_Q);
+        double* tot = at<double>(p.o_rs_tot);
+        int* flag = at<int>(p.o_rs_flag);
+        hipError_t e;
+#define RK(x)                   \
+    do {                        \
+        e = (x);                \
+        if (e != hipSuccess) {  \
+            where = #x;         \
+            return e;           \
+        }                       \
+    } while (0)
+        RK(launch_sumsq(X, dims, dconst(nv * ln), nv * ln, tot, s));
+        RK(launch_sketch(G, ks, nv, (unsigned long long)step, s));
+        // range finder with one subspace iteration, orthonormalised after each product
+        RK(gemm(G, T_F64, X, T_F64, Y, T_F64, dconst(ks), dconst(ln), dconst(nv), 0, 0, 0, ks, ln, P_F64));
+        RK(jacobi(jac(Y, P, dconst(ks), dconst(ln), KS1, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1), ks, ln));
+        RK(gemm(P, T_F64, X, T_F64, T, T_F64, ddyn(KS1), dconst(nv), dconst(ln), 0, 1, 0, ks, nv, P_F64));
+        RK(gemm(T, T_F64, X, T_F64, Y, T_F64, ddyn(KS1), dconst(ln), dconst(nv), 0, 0, 0, ks, ln, P_F64));
+        RK(jacobi(jac(Y, P, ddyn(KS1), dconst(ln), KS2, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1), ks, ln));
+        // B = P X^T; its SVD through the Gram matrix B B^T (gram mode of the Jacobi kernel)
+        RK(gemm(P, T_F64, X, T_F64, T, T_F64, ddyn(KS2), dconst(nv), dconst(ln), 0, 1, 0, ks, nv, P_F64));
+        RK(gemm(T, T_F64, T, T_F64, C, T_F64, ddyn(KS2), ddyn(KS2), dconst(nv), 0, 1, 0, ks, ks, P_F64));
+        JacobiDesc d = jac(C, W, ddyn(KS2), ddyn(KS2), bond + 1, mr, st.tol, st.trunc_mode, step);
+        d.gram = 1;
+        d.total_ext = tot;
+        RK(jacobi(d, ks, ks));
+        RK(gemm(W, T_F64, P, T_F64, Qr, T_F64, ddyn(bond + 1), dconst(ln), ddyn(KS2), 0, 0, 0, ks, ln, P_F64));
+        RK(launch_rsvd_accept(dims, bond + 1, at<double>(p.o_ldelta) + step, tot, ks, RSVD_OVERSAMPLE, st.tol,
+                              st.trunc_mode, at<int>(p.o_status), flag, s));
+        int h = 0;
+        RK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        RK(hipStreamSynchronize(s));
+        *ok = h != 0;
+        if (*ok) {
+            RK(copy(Qr, dest, ddyn(bond + 1), dconst(ln), ks * ln));
+            RK(launch_identity(basis, dims, dconst(ln), ln, s));
+        }
+#undef RK
+        return hipSuccess;
+    }
+
+    // Factorization of one sweep step.  theta holds the rows to orthogonalise
+    // (nvec x len); rotate: pre-rotate by the bond's stored basis (warm start);
+    // randomized: this bond was factorized before in this call and a
+    // randomized method is requested.
+    hipError_t factor(int k, int step, bool rotate, bool randomized, double* theta, DimExpr nvec, DimExpr len,
+                      int nvec_cap, int len_cap, double* dest, int mr) const {
+        if (randomized && !rec) {
+            hipError_t e = read_dims();
+            if (e != hipSuccess) return e;
+            const int nv = eval_host(nvec), ln = eval_host(len);
+            const int ks = sketch_size(k, nv, ln);
+            if (ks > 0) {
+                bool ok = false;
+                e = rsvd(theta, nv, ln, ks, step, k, mr, dest, at<double>(p.o_basis[k]), &ok);
+                if (e != hipSuccess) return e;
+                fact_log[step] = ok ? ks : -ks;
+                if (ok) return hipSuccess;
+            }
+        }
+        double* X = theta;
+        if (rotate) {
+            X = at<double>(p.o_theta2);
+            hipError_t e = gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, nvec, len, nvec, 0, 0, 0, nvec_cap,
+                                len_cap, P_F64);
+            if (e != hipSuccess) return e;
+        }
+        JacobiDesc d = jac(X, dest, nvec, len, k + 1, mr, st.tol, st.trunc_mode, step);
+        d.basis = at<double>(p.o_basis[k]);
+        return jacobi(d, nvec_cap, len_cap);
+    }
+
+    int eval_host(DimExpr x) const { return x.idx < 0 ? x.mul : x.mul * hdims[x.idx]; }
+
     hipError_t run() const {
         const int L = p.L;
         const auto& c = p.capb;
@@ -405,7 +569,7 @@ struct Enq {
             Op op;
             op.kind = OP_SETINTS;
             op.set_base = dims;
-            op.set_vals.assign(L + 2, 0);
+            op.set_vals.assign(L + 4, 0);
             for (int k = 0; k <= L; ++k) op.set_vals[k] = p.chiv[k];
             CK(emit(std::move(op)));
         }
@@ -467,7 +631,14 @@ struct Enq {
         }
         // ---- sweeps (Sec. 2.5)
         int step = 0;
+        const bool rs = p.fact != SMPS_FACT_SVD;
+        if (!rec) fact_log.assign(std::max(1, p.steps), 0);
+        sweeps_done = 0;
         for (int sw = 0; sw < S; ++sw) {
+            // bond k was last factorized in the previous half-sweep, at step
+            // (2 sw - 1)(L - 1) + (L - 2 - k)
+            const bool rs_lr = rs && sw > 0;
+            if (rs_lr && !rec) CK(predict_ranks((2 * sw - 1) * (L - 1) + (L - 2), -1));
             for (int k = 0; k + 1 < L; ++k) {  // left to right
                 tag(3 + 2 * sw, k);
                 CK(build_XL(k));
@@ -476,24 +647,18 @@ struct Enq {
                         ddyn(k + 2, e[k + 1]), dconst(p.Dm[k + 1] * p.chiv[k + 1]), 0, 0, 1, c[k] * e[k],
                         e[k + 1] * c[k + 2], p.prec));
                 const int mr = std::min(st.max_bond, c[k + 1]);
-                // warm start: rotate the columns by the right singular basis this bond
+                // warm start (sw > 0): rotate by the right singular basis this bond
                 // produced in the previous right-to-left pass (identity when it was not full)
-                double* X = theta;
-                if (sw > 0) {
-                    X = at<double>(p.o_theta2);
-                    CK(gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]),
-                            ddyn(k + 2, e[k + 1]), 0, 0, 0, e[k + 1] * c[k + 2], c[k] * e[k], P_F64));
-                }
-                JacobiDesc d = jac(X, at<double>(p.o_Q), ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), k + 1, mr, st.tol,
-                                   st.trunc_mode, step);
-                d.basis = at<double>(p.o_basis[k]);
-                CK(jacobi(d, e[k + 1] * c[k + 2], c[k] * e[k]));
+                CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
+                          c[k] * e[k], at<double>(p.o_Q), mr));
                 // Lenv[k+1] = Q XL[k]
                 CK(gemm(at(p.o_Q), T_F64, at(p.o_XL[k]), p.et, at(p.o_L[k + 1]), p.et, ddyn(k + 1),
                         dconst(p.Dm[k + 1] * p.chiv[k + 1]), ddyn(k, e[k]), 0, 0, 0, c[k + 1],
                         p.Dm[k + 1] * p.chiv[k + 1], p.prec));
                 ++step;
             }
+            // bond k was last factorized in this sweep's left-to-right pass, at step 2 sw (L - 1) + k
+            if (rs && !rec) CK(predict_ranks(2 * sw * (L - 1), 1));
             for (int k = L - 2; k >= 0; --k) {  // right to left
                 tag(4 + 2 * sw, L - 2 - k);
                 CK(build_XR(k + 1, at(p.o_R[k + 2]), at(p.o_tmp), at(p.o_XR[k + 1]), p.et, p.prec));
@@ -503,15 +668,21 @@ struct Enq {
                         e[k + 1] * c[k + 2], p.prec));
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start from the left singular basis of this pass's left-to-right visit
-                double* X = at<double>(p.o_theta2);
-                CK(gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]),
-                        ddyn(k, e[k]), 0, 0, 0, c[k] * e[k], e[k + 1] * c[k + 2], P_F64));
-                JacobiDesc d = jac(X, at<double>(p.o_psi[k + 1]), ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), k + 1, mr,
-                                   st.tol, st.trunc_mode, step);
-                d.basis = at<double>(p.o_basis[k]);
-                CK(jacobi(d, c[k] * e[k], e[k + 1] * c[k + 2]));
+                CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
+                          e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
                 CK(env_R(k + 1, at(p.o_XR[k + 1]), at(p.o_R[k + 1]), p.et, p.prec));
                 ++step;
+            }
+            sweeps_done = sw + 1;
+            steps_done = step;
+            // early stop (single path): relative change of ||psi||^2 over the sweep
+            if (!rec && st.sweep_tol > 0.0 && sw > 0 && L > 1) {
+                double nn[2] = {0.0, 0.0};
+                const int last = step - 1, prev = step - 1 - 2 * (L - 1);
+                CK(hipMemcpyAsync(&nn[0], at<double>(p.o_lnorm2) + last, sizeof(double), hipMemcpyDeviceToHost, s));
+                CK(hipMemcpyAsync(&nn[1], at<double>(p.o_lnorm2) + prev, sizeof(double), hipMemcpyDeviceToHost, s));
+                CK(hipStreamSynchronize(s));
+                if (std::fabs(nn[0] - nn[1]) <= st.sweep_tol * std::fabs(nn[0])) break;
             }
         }
         // ---- centre tensor psi_0 = B_0 A_0 Renv[1]: an exact projection on the
@@ -561,7 +732,7 @@ static const char* status_message(int status) {
 static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy& st, smps_mps** out,
                   double* trunc_err) {
     const int L = p.L;
-    const int steps = p.steps;
+    const int steps = q.steps_done;
     std::vector<int> hd(L + 2);
     int status = 0;
     double norm2 = 0.0;
@@ -602,8 +773,13 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     c->info.error_bound = eb;
     c->info.discarded = disc;
     c->info.norm = std::sqrt(norm2);
-    c->info.sweeps_done = st.max_sweeps;
+    c->info.sweeps_done = q.sweeps_done;
     c->info.steps = steps;
+    c->log_fact.assign(q.fact_log.begin(), q.fact_log.begin() + std::min<size_t>(steps, q.fact_log.size()));
+    for (int f : c->log_fact) {
+        c->info.rsvd_accepted += f > 0;
+        c->info.rsvd_fallbacks += f < 0;
+    }
     for (int i = 0; i < steps; ++i) c->info.jacobi_sweeps += c->log_sweeps[i];
     if (trunc_err) *trunc_err = eb;
     *out = m;
@@ -619,6 +795,9 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
         return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
     int rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
+    if (st.factorization == SMPS_FACT_RSVD_MLP && !mlp_ready(c))
+        return fail(c, SMPS_EINVAL, "the randomized factorization sized by the rank predictor needs "
+                                    "smps_rank_mlp_init, _set or _train first");
     Enq q{p, U, v, st, c->arena, c->stream, (int*)(c->arena + p.o_dims)};
     q.ctx = c;
     hipError_t e = q.run();
@@ -907,6 +1086,8 @@ void batch_cache_free(smps_ctx* c) {
 
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                       const smps_strategy& st, smps_mps** out, double* trunc_err) {
+    if (st.factorization != SMPS_FACT_SVD)
+        return fail(c, SMPS_EUNSUPPORTED, "the batched path uses the exact factorization only");
     if (n == 0) return SMPS_OK;
     // ---- plans of all problems in one workspace
     std::vector<Plan> plans(n);
@@ -1054,6 +1235,7 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
     c->info = smps_apply_info{};
     c->info.steps = (int)steps_total;
     c->info.sweeps_done = st.max_sweeps;
+    c->log_fact.clear();
     c->log_delta.clear();
     c->log_rank.clear();
     c->log_spec.clear();

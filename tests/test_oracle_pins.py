@@ -345,3 +345,100 @@ def test_adam_constant_gradient_moves_by_lr_per_step():
         p_new, m, v = adam_step(p, g, m, v, t, lr)
         np.testing.assert_allclose(p - p_new, lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
         p = p_new
+
+
+# ---- randomized factorization (oracle/rsvd.py) ---------------------------------
+
+def test_philox_matches_numpy_bit_generator():
+    """Philox4x64-10 pinned to numpy's independent implementation (which
+    advances the counter before producing a block)."""
+    from oracle import rsvd
+    for ctr, key in [((0, 0, 0, 0), (0, 0)), ((5, 3, 0, 0), (7, 9)), ((2**64 - 2, 1, 2, 3), (2**63, 12345))]:
+        bg = np.random.Philox(counter=np.array(ctr, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
+        raw = [int(x) for x in bg.random_raw(4)]
+        nxt = (ctr[0] + 1) % 2**64
+        assert rsvd.philox4x64_10_scalar((nxt,) + tuple(ctr[1:]), key) == raw
+        v = rsvd.philox4x64_10(np.array([nxt], dtype=np.uint64), np.array([ctr[1]], dtype=np.uint64),
+                               np.array([ctr[2]], dtype=np.uint64), np.array([ctr[3]], dtype=np.uint64), key)
+        assert [int(x[0]) for x in v] == raw
+
+
+def test_sketch_gaussians_moments():
+    from oracle import rsvd
+    g = rsvd.gaussians(3, 400_000)
+    assert abs(g.mean()) < 6e-3 and abs(g.var() - 1.0) < 1e-2
+    assert abs(np.mean(np.abs(g) < 1.0) - 0.682689) < 4e-3
+    assert abs(np.mean(g ** 4) - 3.0) < 5e-2
+    # different steps give different streams, the same step the same one
+    assert not np.allclose(rsvd.gaussians(4, 64), rsvd.gaussians(3, 64))
+    assert np.array_equal(rsvd.gaussians(3, 64), g[:64])
+
+
+def test_rank_with_total_hand_values():
+    from oracle import rsvd
+    from oracle.mps import REL_NORM2
+    # s^2 = 9, 4, 1, missed weight 0.5, total 14.5, threshold 1.6:
+    # tails with the missed weight: r=1 -> 5.5, r=2 -> 1.5 (fits), so r = 2
+    r, d = rsvd.rank_with_total([3.0, 2.0, 1.0], 14.5, 1.6 / 14.5, 10, REL_NORM2)
+    assert r == 2 and abs(d - 1.5) < 1e-15
+    # the missed weight alone above the threshold: keep everything
+    r, d = rsvd.rank_with_total([3.0, 2.0, 1.0], 20.0, 0.1, 10, REL_NORM2)
+    assert r == 3 and abs(d - 6.0) < 1e-12
+
+
+def test_rsvd_equals_exact_svd_when_sketch_covers_rank():
+    from oracle import rsvd
+    from oracle.mps import REL_NORM2, svd_desc
+    rng = np.random.default_rng(21)
+    for rank, (m, n) in [(8, (60, 90)), (5, (120, 40)), (12, (64, 64))]:
+        X = rng.standard_normal((m, rank)) @ np.diag(np.geomspace(10, 0.1, rank)) @ rng.standard_normal((rank, n))
+        Q, s, r, delta, ok = rsvd.rsvd_rows(X, rank + 16, 1e-12, 100, REL_NORM2, step=7)
+        _, S, Vt = svd_desc(X)
+        assert ok and r == rank
+        np.testing.assert_allclose(s[:rank], S[:rank], rtol=1e-12)
+        # same row space: equal projectors
+        assert np.max(np.abs(Q.T @ Q - Vt[:rank].T @ Vt[:rank])) < 1e-10
+        assert np.max(np.abs(Q @ Q.T - np.eye(rank))) < 1e-12
+
+
+def test_rsvd_discarded_weight_is_the_projection_error():
+    """delta = ||X||^2 - sum_{j<r} s_j^2 must equal ||X - X Q^T Q||_F^2 for the
+    returned Q, also when the sketch misses part of the spectrum."""
+    from oracle import rsvd
+    from oracle.mps import REL_NORM2, REL_SV
+    rng = np.random.default_rng(8)
+    U, _ = np.linalg.qr(rng.standard_normal((80, 80)))
+    V, _ = np.linalg.qr(rng.standard_normal((100, 80)))
+    X = U @ np.diag(np.exp(-np.arange(80) / 6.0)) @ V.T
+    for k, mode, tol in [(30, REL_NORM2, 1e-8), (20, REL_NORM2, 1e-12), (24, REL_SV, 1e-3)]:
+        Q, s, r, delta, ok = rsvd.rsvd_rows(X, k, tol, 100, mode, step=1)
+        err = np.sum((X - X @ Q.T @ Q) ** 2)
+        assert abs(err - delta) <= 1e-12 * np.sum(X * X) + 1e-6 * err
+    # the sketch of 20 cannot reach a 1e-12 relative tail here: rejected
+    assert not rsvd.rsvd_rows(X, 20, 1e-12, 100, REL_NORM2, step=1)[4]
+
+
+def _decaying_identity_case(L=16, chi=64, taus=(3.0, 6.0), seed=4):
+    rng = np.random.default_rng(seed)
+    mps, _ = synth.decaying_spectrum_mps(rng, L, 2, chi, tau_range=taus)
+    return mps, synth.identity_mpo(L, 2)
+
+
+def test_sketched_sweep_matches_exact_sweep_when_sketches_are_accepted():
+    """Compressing a state with fast-decaying spectra (tolerance-bound ranks
+    of about 25 on 50 x 50 two-site matrices): accepted randomized splits must
+    reproduce the exact sweep to rounding."""
+    from oracle import rsvd
+    from oracle.mps import apply_simplify
+    mps, mpo = _decaying_identity_case()
+    L = len(mps)
+    exact = apply_simplify(mpo, mps, 64, 1e-10, sweeps=2)
+    for predictor in (lambda f: np.log(24.5), None):
+        hook = rsvd.SketchedSplit(64, 1e-10, predictor=predictor)
+        got = apply_simplify(mpo, mps, 64, 1e-10, sweeps=2, split_hook=hook)
+        assert hook.kinds[:L - 1] == [0] * (L - 1)
+        assert sum(k > 0 for k in hook.kinds) >= 10
+        assert got.ranks == exact.ranks
+        assert abs(got.norm - exact.norm) < 1e-12 * exact.norm
+        f = om.scprod(got.mps, exact.mps) / (got.norm * exact.norm)
+        assert abs(1 - f) < 1e-12
