@@ -38,21 +38,43 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (no parity check, no baseline)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU baseline: repeat the oracle until this much time has passed")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
 
 
 def svd_flops(m: int, n: int) -> float:
-    """Algorithmic flops of one factorization of an m x n two-site tensor:
-    20 k^2 l with k = min(m, n), l = max(m, n) (20 (d chi)^3 when square)."""
+    """Algorithmic flops of one factorization of an m x n two-site tensor
+    that yields the singular values and one set of singular vectors:
+    4 l k^2 + 8 k^3 with k = min(m, n), l = max(m, n) (the R-SVD count of
+    Golub & Van Loan, Matrix Computations, 4th ed., Fig. 8.6.1)."""
     k, l = min(m, n), max(m, n)
-    return 20.0 * k * k * l
+    return 4.0 * l * k * k + 8.0 * k ** 3
+
+
+def copy_probe(mib: int):
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 4}))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
+        print("bench.py measures one GPU (the method's sweep is sequential along the chain and no multi-GPU "
+              "path is built); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import numpy as np
     import torch
@@ -83,11 +105,16 @@ def main():
         except Exception:
             cores = os.cpu_count()
         t0 = time.perf_counter()
-        ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=w.sweeps)
-        dt = time.perf_counter() - t0
+        reps = 0
+        while True:
+            ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=w.sweeps)
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = (time.perf_counter() - t0) / reps
         cpu = {"value": site_updates / dt, "unit": "site-updates/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"one full apply+compress of the same workload ({site_updates} site-updates, "
-                         f"{dt:.1f} s, FP64 NumPy/SciPy)"}
+               "sample": f"{reps} full apply+compress runs of the same workload ({site_updates} site-updates "
+                         f"each, {dt:.2f} s per run, FP64 NumPy/SciPy)"}
 
     # theta shapes along the sweep (bond dims reach the cap for this workload)
     caps = synth.bond_caps(L, 2, w.max_bond)
@@ -157,7 +184,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": f"{best_p} contractions, f64 factorization",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[best_p],
         "data": "synthetic",
         "config": {"workload": "random MPO D=8 on random MPS n=20 d=2 chi=64, max bond 64, tol 1e-10, 4 sweeps",
                    "site_updates_per_step": site_updates, "precision": best_p},
