@@ -54,6 +54,20 @@ def svd_flops(m: int, n: int) -> float:
     return 4.0 * l * k * k + 8.0 * k ** 3
 
 
+def measured_traffic(path: str, source: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (None otherwise)."""
+    import hashlib
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith(" "))
+        sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256", "").strip() != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def copy_probe(mib: int):
     import torch
     n = mib * (1 << 20) // 4
@@ -168,9 +182,11 @@ def main():
     fact_avg_ms = f["factorization_ms_per_step"] / max(1e-9, f["factorization_launches_per_step"])
     flops_per_launch = flops_per_apply / max(1e-9, f["factorization_launches_per_step"])
     achieved = flops_per_launch / (fact_avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "jacobi_lds_kernel (FP64 one-sided Jacobi SVD, one workgroup per factorization)",
+    roofline = {"kernel": "jacobi_lds_kernel<E> (FP64 one-sided Jacobi SVD, one workgroup per factorization)",
                 "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": measured_traffic(os.path.join(ROOT, "profiles", "jacobi_lds_c2_traffic.txt"),
+                                            os.path.join(ROOT, "paper_2601_16734_amd", "csrc", "jacobi.hip")),
                 "avg_launch_ms": fact_avg_ms, "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"]}
 
     line = {
