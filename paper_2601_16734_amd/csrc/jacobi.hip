@@ -28,7 +28,10 @@
 
 namespace smps {
 
-constexpr int JT = 1024;               // threads per Jacobi workgroup
+constexpr int JT = 1024;               // threads per Jacobi workgroup (blocked path, select)
+// threads of the LDS-resident kernel for length class 16 E: 1024, except the
+// widest class, whose two register-held rows would not fit 128 VGPRs per lane
+__host__ __device__ constexpr int lds_threads(int E) { return E >= 16 ? 512 : 1024; }
 constexpr int LDS_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr int JAC_MAX_SWEEPS = 40;
 constexpr int SEL_MAX = 2048;          // vectors handled by the select kernel
@@ -68,42 +71,173 @@ __device__ __forceinline__ double row_sum16(double x) {
     return x;
 }
 
+// Sum over the 8 lanes of a half row (quad pairs, then the half-row mirror).
+__device__ __forceinline__ double row_sum8(double x) {
+    x += dpp_mov<0xB1>(x);
+    x += dpp_mov<0x4E>(x);
+    x += dpp_mov<0x141>(x);
+    return x;
+}
+__device__ __forceinline__ double row_sum4(double x) {
+    x += dpp_mov<0xB1>(x);
+    x += dpp_mov<0x4E>(x);
+    return x;
+}
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+    if constexpr (G == 16) return row_sum16(x);
+    else if constexpr (G == 8) return row_sum8(x);
+    else return row_sum4(x);
+}
+
+// Rutishauser's rotation for a pair with squared norms a, b and dot product c:
+// t = sgn(z) / (|z| + sqrt(1 + z^2)), z = (b - a) / 2c, written as
+// t = sgn(b - a) 2c / (|b - a| + sqrt((b - a)^2 + 4c^2)).  That form is
+// homogeneous of degree 0, so both terms are first scaled by an approximate
+// 1 / max(|b - a|, |2c|) (no overflow or underflow), and the square root and
+// the quotient use the hardware approximations with one Newton step each.
+// cs = 1 / sqrt(1 + t^2) gets its own Newton step so that cs^2 + sn^2 = 1 to
+// rounding: that, not the exact angle, keeps the transformation orthogonal.
+__device__ __forceinline__ void jacobi_rotation(double a, double b, double c, double& cs, double& sn, double& t) {
+    const double d = b - a, c2 = c + c;
+    const double r = __builtin_amdgcn_rcp(fmax(fabs(d), fabs(c2)));
+    const double dn = d * r, cn = c2 * r;
+    const double hh = fma(dn, dn, cn * cn);
+    double rs = __builtin_amdgcn_rsq(hh);
+    rs = rs * fma(-0.5 * hh * rs, rs, 1.5);
+    const double den = fma(hh, rs, fabs(dn));
+    double rc = __builtin_amdgcn_rcp(den);
+    rc = rc * fma(-den, rc, 2.0);
+    t = (d >= 0.0 ? cn : -cn) * rc;
+    const double h = fma(t, t, 1.0);
+    cs = __builtin_amdgcn_rsq(h);
+    cs = cs * fma(-0.5 * h * cs, cs, 1.5);
+    sn = cs * t;
+}
+
+// |c| > tol sqrt(a b); the square roots only set a threshold, so the hardware
+// reciprocal square roots are used as they are.
+__device__ __forceinline__ bool jacobi_needs_rotation(double a, double b, double c, double tol) {
+    return fabs(c) > tol * (a * __builtin_amdgcn_rsq(a)) * (b * __builtin_amdgcn_rsq(b));
+}
+
+__device__ __forceinline__ int pow2_ceil(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
 // Orthogonalise nv vectors (row j at W + j*ld, length len) held in LDS; nrm
 // (nv doubles of LDS) holds their squared norms, recomputed exactly at the
 // start of every sweep and updated in between by the exact 2x2 relations
 // (a' = a - t c, b' = b + t c), so a pair needs one dot product only.
-// A group of 16 lanes (one DPP row) handles a pair; the pairs of a round of
-// the round-robin tournament are disjoint and run concurrently.
-// E > 0: each lane keeps its E elements of both vectors in registers between
-// the dot product and the rotation (len <= 16 E); E = 0: generic strided loop.
+// A group of G lanes (G = 4, 8 or 16, inside one DPP row) handles a pair;
+// the pairs of a round are disjoint and run concurrently.  E > 0: each lane
+// keeps its E elements of both vectors in registers between the dot product
+// and the rotation (rows zero padded to ld = G E); E = 0: generic strided loop.
+//
+// Pair orderings (every pair once per sweep):
+// * home/away (E > 0, P = pairs padded to a power of two, all P groups
+//   resident): stage h = P, P/2, ..., 1 cuts the rows into sets of 2h; in a
+//   set, group i keeps row i of the lower half in registers for the whole
+//   stage and meets row (i + r) mod h of the upper half in round r.  Only the
+//   visiting row goes through LDS, half the traffic of moving both rows.
+// * round-robin tournament (otherwise).
 // Returns (block-uniform) the number of sweeps that applied a rotation.
-template <int E>
+template <int E, int G = 16>
 __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double floor2,
                              int true_len, int max_sweeps = JAC_MAX_SWEEPS) {
+    static_assert(G == 4 || G == 8 || G == 16, "group width");
+    static_assert(E > 0 || G == 16, "generic path uses 16-lane groups");
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
     // cosine threshold: rounding in a length-n dot product is ~eps*sqrt(n); eps*n leaves margin
     const double tol = DBL_EPSILON * (double)(true_len > 16 ? true_len : 16);
     const double tiny = fmax(DBL_MIN * 1.0e4, floor2);
     const int P = (nv + 1) / 2, n2 = 2 * P;
-    constexpr int g = 16;
-    const int gl = tid & (g - 1), gi = tid / g, ngroups = JT / g;
+    const int nt = blockDim.x;
+    const int gl = tid & (G - 1), gi = tid / G, ngroups = nt / G;
+    const int P2 = pow2_ceil(P);
+    const bool home_away = E > 0 && P2 <= ngroups && 4 * P2 <= 5 * P;
     int any = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        for (int j = gi; j < nv; j += ngroups) {
-            const double* w = W + j * ld;
-            double a0 = 0.0, a1 = 0.0;
-            int i = gl;
-            for (; i + g < len; i += 2 * g) {
-                a0 = fma(w[i], w[i], a0);
-                a1 = fma(w[i + g], w[i + g], a1);
+        {
+            constexpr int g = 16;
+            const int hl = tid & (g - 1), hi = tid / g;
+            for (int j = hi; j < nv; j += nt / g) {
+                const double* w = W + j * ld;
+                double a0 = 0.0, a1 = 0.0;
+                int i = hl;
+                for (; i + g < len; i += 2 * g) {
+                    a0 = fma(w[i], w[i], a0);
+                    a1 = fma(w[i + g], w[i + g], a1);
+                }
+                if (i < len) a0 = fma(w[i], w[i], a0);
+                const double a = row_sum16(a0 + a1);
+                if (hl == 0) nrm[j] = a;
             }
-            if (i < len) a0 = fma(w[i], w[i], a0);
-            const double a = row_sum16(a0 + a1);
-            if (gl == 0) nrm[j] = a;
         }
         if (tid == 0) *s_flag = 0;
         __syncthreads();
+        if constexpr (E > 0) {
+            if (home_away) {
+                for (int h = P2; h >= 1; h >>= 1) {
+                    const int set = gi / h, i = gi - set * h;
+                    const int home = set * 2 * h + i;
+                    const bool act = gi < P2 && home < nv;
+                    double x[E];
+                    double a = 0.0;
+                    if (act) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) x[e] = W[home * ld + gl + G * e];
+                        a = nrm[home];
+                    }
+                    for (int r = 0; r < h; ++r) {
+                        const int q = set * 2 * h + h + ((i + r) & (h - 1));
+                        if (act && q < nv) {
+                            const double b = nrm[q];
+                            if (a > tiny && b > tiny) {  // uniform in the group
+                                double* wq = W + q * ld;
+                                double y[E];
+                                double cc[2] = {0.0, 0.0};
+#pragma unroll
+                                for (int e = 0; e < E; ++e) y[e] = wq[gl + G * e];
+#pragma unroll
+                                for (int e = 0; e < E; ++e) cc[e & 1] = fma(x[e], y[e], cc[e & 1]);
+                                const double c = group_sum<G>(cc[0] + cc[1]);
+                                if (jacobi_needs_rotation(a, b, c, tol)) {
+                                    double cs, sn, t;
+                                    jacobi_rotation(a, b, c, cs, sn, t);
+#pragma unroll
+                                    for (int e = 0; e < E; ++e) {
+                                        const double xe = x[e];
+                                        x[e] = cs * xe - sn * y[e];
+                                        wq[gl + G * e] = sn * xe + cs * y[e];
+                                    }
+                                    a = fmax(a - t * c, 0.0);
+                                    if (gl == 0) {
+                                        nrm[q] = b + t * c;
+                                        *s_flag = 1;
+                                    }
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                    if (act) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) W[home * ld + gl + G * e] = x[e];
+                        if (gl == 0) nrm[home] = a;
+                    }
+                    __syncthreads();
+                }
+                const int rot = *s_flag;
+                __syncthreads();
+                if (!rot) break;
+                ++any;
+                continue;
+            }
+        }
         for (int rd = 0; rd < n2 - 1; ++rd) {
             for (int pi = gi; pi < P; pi += ngroups) {
                 const int p = tourney(pi, rd, n2), q = tourney(n2 - 1 - pi, rd, n2);
@@ -118,42 +252,35 @@ __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, in
                     double cc[2] = {0.0, 0.0};
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const int i = gl + g * e;  // len == 16 E here (zero padded)
+                        const int i = gl + G * e;  // len == G E here (zero padded)
                         x[e] = wp[i];
                         y[e] = wq[i];
                     }
 #pragma unroll
                     for (int e = 0; e < E; ++e) cc[e & 1] = fma(x[e], y[e], cc[e & 1]);
-                    c = row_sum16(cc[0] + cc[1]);
+                    c = group_sum<G>(cc[0] + cc[1]);
                 } else {
                     double c0 = 0.0, c1 = 0.0;
                     int i = gl;
-                    for (; i + g < len; i += 2 * g) {
+                    for (; i + G < len; i += 2 * G) {
                         c0 = fma(wp[i], wq[i], c0);
-                        c1 = fma(wp[i + g], wq[i + g], c1);
+                        c1 = fma(wp[i + G], wq[i + G], c1);
                     }
                     if (i < len) c0 = fma(wp[i], wq[i], c0);
-                    c = row_sum16(c0 + c1);
+                    c = group_sum<G>(c0 + c1);
                 }
-                if (fabs(c) > tol * sqrt(a * b)) {
-                    // Rutishauser's rotation: t = sgn(z) / (|z| + sqrt(1 + z^2)), z = (b - a) / 2c;
-                    // c^2 + s^2 = 1 is what keeps the transformation orthogonal, so
-                    // cs = 1/sqrt(1 + t^2) gets a Newton step after the hardware rsqrt.
-                    const double zeta = (b - a) / (2.0 * c);
-                    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double h = 1.0 + t * t;
-                    double cs = __builtin_amdgcn_rsq(h);
-                    cs = cs * fma(-0.5 * h * cs, cs, 1.5);
-                    const double sn = cs * t;
+                if (jacobi_needs_rotation(a, b, c, tol)) {
+                    double cs, sn, t;
+                    jacobi_rotation(a, b, c, cs, sn, t);
                     if constexpr (E > 0) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) {
-                            const int i = gl + g * e;
+                            const int i = gl + G * e;
                             wp[i] = cs * x[e] - sn * y[e];
                             wq[i] = sn * x[e] + cs * y[e];
                         }
                     } else {
-                        for (int i = gl; i < len; i += g) {
+                        for (int i = gl; i < len; i += G) {
                             const double xv = wp[i], yv = wq[i];
                             wp[i] = cs * xv - sn * yv;
                             wq[i] = sn * xv + cs * yv;
@@ -188,12 +315,13 @@ static int elems_for(int len_cap) {
 
 // Norms, order, rank rule and discarded weight for nv vectors; results in
 // LDS arrays sig (sorted order), perm, and the returned rank.  W may be in
-// LDS or global memory.  Must be called by all JT threads.
+// LDS or global memory.  Must be called by all threads of the workgroup.
 __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* sig_raw, double* sig_sorted,
                              int* perm, const JacobiDesc& d, double* s_delta) {
     const int tid = threadIdx.x;
     // norms: a group of 16 lanes per vector
-    const int g = 16, gl = tid & (g - 1), gi = tid / g, ngroups = JT / g;
+    const int nt = blockDim.x;
+    const int g = 16, gl = tid & (g - 1), gi = tid / g, ngroups = nt / g;
     for (int j = gi; j < nv; j += ngroups) {
         const double* w = W + (size_t)j * ld;
         double a = 0.0;
@@ -210,13 +338,13 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
         s_floor2 = zero_floor2(t2, nv, len, d.floor_eps);
     }
     __syncthreads();
-    for (int j = tid; j < nv; j += JT) {
+    for (int j = tid; j < nv; j += nt) {
         const double a = sig_raw[j];
         sig_raw[j] = a > s_floor2 ? (d.gram ? sqrt(sqrt(a)) : sqrt(a)) : 0.0;
     }
     __syncthreads();
     // descending order with ties broken by index
-    for (int j = tid; j < nv; j += JT) {
+    for (int j = tid; j < nv; j += nt) {
         const double sj = sig_raw[j];
         int pos = 0;
         for (int k = 0; k < nv; ++k) {
@@ -278,8 +406,8 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
     }
     __syncthreads();
     if (d.log_spec)
-        for (int j = tid; j < 32; j += JT) d.log_spec[j] = j < nv ? sig_sorted[j] : 0.0;
-    for (int j = tid; j < nv; j += JT) d.sigma[j] = sig_sorted[j];
+        for (int j = tid; j < 32; j += nt) d.log_spec[j] = j < nv ? sig_sorted[j] : 0.0;
+    for (int j = tid; j < nv; j += nt) d.sigma[j] = sig_sorted[j];
     const int r = s_r;
     __syncthreads();
     return r;
@@ -289,7 +417,7 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
 // whole matrix is zero and one row is kept: it becomes the first unit vector).
 __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, const double* sig_sorted,
                                   const int* perm, int r, double* Q, double* basis, int gram) {
-    for (size_t e = threadIdx.x; e < (size_t)r * len; e += JT) {
+    for (size_t e = threadIdx.x; e < (size_t)r * len; e += blockDim.x) {
         const int i = (int)(e / len), l = (int)(e % len);
         const double s = gram ? sig_sorted[i] * sig_sorted[i] : sig_sorted[i];
         Q[e] = s > 0.0 ? W[(size_t)perm[i] * ld + l] / s : (l == i ? 1.0 : 0.0);
@@ -298,14 +426,15 @@ __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, cons
     // len x len basis for the next visit of this bond: every normalised vector
     // when they span the whole space, else the identity (no warm start)
     const bool full = nv >= len && sig_sorted[len - 1] > 0.0;
-    for (size_t e = threadIdx.x; e < (size_t)len * len; e += JT) {
+    for (size_t e = threadIdx.x; e < (size_t)len * len; e += blockDim.x) {
         const int i = (int)(e / len), l = (int)(e % len);
         basis[e] = full ? W[(size_t)perm[i] * ld + l] / sig_sorted[i] : (l == i ? 1.0 : 0.0);
     }
 }
 
 template <int E>
-__global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+__global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+    constexpr int LDS_NT = lds_threads(E);
     extern __shared__ double sm[];
     const JacobiDesc d = arr ? arr[blockIdx.x] : d0;  // batched: one factorization per workgroup
     __shared__ int s_flag, s_bad;
@@ -321,7 +450,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
     if (tid == 0) s_bad = 0;
     __syncthreads();
     int bad = 0;
-    for (int e = tid; e < nv * ld; e += JT) {
+    for (int e = tid; e < nv * ld; e += LDS_NT) {
         const int j = e / ld, i = e - j * ld;
         double x = 0.0;
         if (i < len) {
@@ -333,7 +462,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
     if (bad) s_bad = 1;
     __syncthreads();
     if (s_bad) {
-        for (int e = tid; e < nv * ld; e += JT) W[e] = 0.0;
+        for (int e = tid; e < nv * ld; e += LDS_NT) W[e] = 0.0;
         if (tid == 0 && d.status) *d.status = 1;
         __syncthreads();
     }
@@ -341,7 +470,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
     __shared__ double s_total2;
     {
         const int gl = tid & 15, gi = tid >> 4;
-        for (int j = gi; j < nv; j += JT / 16) {
+        for (int j = gi; j < nv; j += LDS_NT / 16) {
             double a = 0.0;
             for (int i = gl; i < len; i += 16) a = fma(W[j * ld + i], W[j * ld + i], a);
             a = row_sum16(a);
@@ -355,7 +484,7 @@ __global__ __launch_bounds__(JT) void jacobi_lds_kernel(JacobiDesc d0, const Jac
         }
         __syncthreads();
     }
-    const int nsw = jacobi_orth_t<E>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag,
+    const int nsw = jacobi_orth_t<E, 16>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag,
                                       zero_floor2(s_total2, nv, len, d.floor_eps), len);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
@@ -549,7 +678,7 @@ void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) 
 size_t jacobi_work_doubles(int, int) { return 0; }
 
 static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
-    const dim3 g(count), b(JT);
+    const dim3 g(count), b(lds_threads(E));
     switch (E) {
         case 1: hipLaunchKernelGGL(jacobi_lds_kernel<1>, g, b, shm, s, d, arr); break;
         case 2: hipLaunchKernelGGL(jacobi_lds_kernel<2>, g, b, shm, s, d, arr); break;
