@@ -68,11 +68,11 @@ enum {
     SMPS_FACT_RSVD_MLP = 1,   /* randomized SVD sized by the rank predictor, exact SVD as fallback */
     SMPS_FACT_RSVD_PREV = 2   /* randomized SVD sized by the bond's previous kept rank, exact fallback */
 };
-/* Randomized factorization (single-problem path only): range finder with one
-   subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4) on a Gaussian
-   sketch of k = r + 16 rows drawn from Philox4x64-10 (counter (block, step, 0, 0)),
-   orthonormalised by the Jacobi kernel, then the SVD of the small projected
-   matrix.  r is the predicted rank: ceil(exp(output)) of the rank predictor on
+/* Randomized factorization (single-problem path only): Gaussian range finder
+   (Halko, Martinsson & Tropp 2011, Alg. 4.1 with oversampling 16) on a sketch
+   of k = r + 16 rows drawn from Philox4x64-10 (counter (block, step, 0, 0)),
+   orthonormalised by two Gram passes (k x k Jacobi eigenproblems), then the
+   SVD of the projected matrix (Rayleigh-Ritz) through its k x k Gram matrix.  r is the predicted rank: ceil(exp(output)) of the rank predictor on
    the bond's previous spectrum (RSVD_MLP), or the bond's previous kept rank
    (RSVD_PREV).  The step is exact when r >= min(max_bond, m, n) (a rank at the
    cap cannot meet the tolerance) or k >= min(m, n).  The discarded weight

@@ -12,6 +12,9 @@ Sec. 5.1), written for the row space of X (nvec x len):
     B = P X^T = W diag(s) Z^T       small SVD
     Q = W[:, :r]^T P                r from the truncation rule
 
+with q = 0 (POWER_ITERS): the device orthonormalises through Gram matrices,
+which square the condition number, and a power step would square it again.
+
 with ||X||_F^2 - sum_{j<r} s_j^2 as the (exact) discarded weight.  The step
 is accepted when that weight is within the tolerance (relative-norm rule) and
 r <= k - p/2 (p = oversampling); otherwise the caller falls back to the exact
@@ -35,7 +38,7 @@ PHILOX_M = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
 PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
 SKETCH_KEY = (0x0260116734000001, 0x00000000005EE95D)
 OVERSAMPLE = 16
-POWER_ITERS = 1
+POWER_ITERS = 0
 M64 = (1 << 64) - 1
 
 

@@ -164,8 +164,11 @@ hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipSt
 // randomized factorization pieces (rsvd.hip)
 hipError_t launch_sketch(double* G, int rows, int nvec, unsigned long long step, hipStream_t s);
 hipError_t launch_rank_features(const double* lspec, int first, int stride, int count, float* feats, hipStream_t s);
-hipError_t launch_rsvd_accept(const int* dims, int rank_idx, const double* delta, const double* total, int ksketch,
-                              int oversample, double tol, int mode, const int* status, int* flag, hipStream_t s);
+hipError_t launch_rsvd_accept(const int* dims, int rank_idx, const double* delta, const double* total,
+                              const double* sigma, int ksketch, int oversample, double tol, int mode,
+                              const int* status, int* flag, hipStream_t s);
+hipError_t launch_scale_rows(double* W, const double* sigma, const int* dims, DimExpr rows, DimExpr cols, int cap,
+                             hipStream_t s);
 hipError_t launch_identity(double* B, const int* dims, DimExpr n, int cap, hipStream_t s);
 constexpr int RSVD_OVERSAMPLE = 16;
 }  // namespace smps

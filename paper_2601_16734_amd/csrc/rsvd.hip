@@ -91,20 +91,39 @@ hipError_t launch_rank_features(const double* lspec, int first, int stride, int 
     return hipGetLastError();
 }
 
-// accepted = r <= k - p/2 and (relative-norm rule: discarded <= tol * total)
+// accepted = r <= k - p/2, the last kept value is nonzero (a zero one would
+// leave a zero row in the isometry) and (relative-norm rule) discarded <= tol * total
 __global__ void rsvd_accept_kernel(const int* dims, int rank_idx, const double* delta, const double* total,
-                                   int ksketch, int oversample, double tol, int mode, const int* status, int* flag) {
+                                   const double* sigma, int ksketch, int oversample, double tol, int mode,
+                                   const int* status, int* flag) {
     const int r = dims[rank_idx];
-    bool ok = r <= ksketch - oversample / 2;
+    bool ok = r <= ksketch - oversample / 2 && sigma[r - 1] > 0.0;
     if (mode == SMPS_TRUNC_REL_NORM2) ok = ok && *delta <= tol * *total;
     if (status && *status) ok = false;
     *flag = ok ? 1 : 0;
 }
 
-hipError_t launch_rsvd_accept(const int* dims, int rank_idx, const double* delta, const double* total, int ksketch,
-                              int oversample, double tol, int mode, const int* status, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(rsvd_accept_kernel, dim3(1), dim3(1), 0, s, dims, rank_idx, delta, total, ksketch,
+hipError_t launch_rsvd_accept(const int* dims, int rank_idx, const double* delta, const double* total,
+                              const double* sigma, int ksketch, int oversample, double tol, int mode,
+                              const int* status, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(rsvd_accept_kernel, dim3(1), dim3(1), 0, s, dims, rank_idx, delta, total, sigma, ksketch,
                        oversample, tol, mode, status, flag);
+    return hipGetLastError();
+}
+
+// W[j][i] /= s_j for j < rows, i < cols (row-major, ld = cols); zero s_j gives a zero row
+__global__ void scale_rows_kernel(double* W, const double* sigma, const int* dims, DimExpr rows_e, DimExpr cols_e) {
+    const int rows = eval_dim(dims, rows_e), cols = eval_dim(dims, cols_e);
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)rows * cols) return;
+    const double sj = sigma[e / cols];
+    W[e] = sj > 0.0 ? W[e] / sj : 0.0;
+}
+
+hipError_t launch_scale_rows(double* W, const double* sigma, const int* dims, DimExpr rows, DimExpr cols, int cap,
+                             hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scale_rows_kernel, dim3((cap + 255) / 256), dim3(256), 0, s, W, sigma, dims, rows, cols);
     return hipGetLastError();
 }
 

@@ -488,21 +488,37 @@ struct Enq {
     } while (0)
         RK(launch_sumsq(X, dims, dconst(nv * ln), nv * ln, tot, s));
         RK(launch_sketch(G, ks, nv, (unsigned long long)step, s));
-        // range finder with one subspace iteration, orthonormalised after each product
+        // range finder Y = G X, orthonormalised by two Gram passes: C = Y Y^T = V L V^T
+        // (Jacobi in Gram mode), P = L^(-1/2) V^T Y; the second pass on P restores
+        // orthonormality lost to the squared condition number of the first
+        double* sig = at<double>(p.o_sigma);
         RK(gemm(G, T_F64, X, T_F64, Y, T_F64, dconst(ks), dconst(ln), dconst(nv), 0, 0, 0, ks, ln, P_F64));
-        RK(jacobi(jac(Y, P, dconst(ks), dconst(ln), KS1, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1), ks, ln));
-        RK(gemm(P, T_F64, X, T_F64, T, T_F64, ddyn(KS1), dconst(nv), dconst(ln), 0, 1, 0, ks, nv, P_F64));
-        RK(gemm(T, T_F64, X, T_F64, Y, T_F64, ddyn(KS1), dconst(ln), dconst(nv), 0, 0, 0, ks, ln, P_F64));
-        RK(jacobi(jac(Y, P, ddyn(KS1), dconst(ln), KS2, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1), ks, ln));
-        // B = P X^T; its SVD through the Gram matrix B B^T (gram mode of the Jacobi kernel)
-        RK(gemm(P, T_F64, X, T_F64, T, T_F64, ddyn(KS2), dconst(nv), dconst(ln), 0, 1, 0, ks, nv, P_F64));
+        RK(gemm(Y, T_F64, Y, T_F64, C, T_F64, dconst(ks), dconst(ks), dconst(ln), 0, 1, 0, ks, ks, P_F64));
+        {
+            JacobiDesc g1 = jac(C, W, dconst(ks), dconst(ks), KS1, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1);
+            g1.gram = 1;
+            RK(jacobi(g1, ks, ks));
+        }
+        RK(launch_scale_rows(W, sig, dims, ddyn(KS1), dconst(ks), ks * ks, s));
+        RK(gemm(W, T_F64, Y, T_F64, P, T_F64, ddyn(KS1), dconst(ln), dconst(ks), 0, 0, 0, ks, ln, P_F64));
+        RK(gemm(P, T_F64, P, T_F64, C, T_F64, ddyn(KS1), ddyn(KS1), dconst(ln), 0, 1, 0, ks, ks, P_F64));
+        {
+            JacobiDesc g2 = jac(C, W, ddyn(KS1), ddyn(KS1), KS2, ks, 0.0, SMPS_TRUNC_REL_NORM2, -1);
+            g2.gram = 1;
+            RK(jacobi(g2, ks, ks));
+        }
+        RK(launch_scale_rows(W, sig, dims, ddyn(KS2), ddyn(KS1), ks * ks, s));
+        RK(gemm(W, T_F64, P, T_F64, Y, T_F64, ddyn(KS2), dconst(ln), ddyn(KS1), 0, 0, 0, ks, ln, P_F64));
+        // Rayleigh-Ritz: B = P X^T (P now in Y); SVD of B through B B^T with the
+        // truncation rule and the exact total ||X||_F^2
+        RK(gemm(Y, T_F64, X, T_F64, T, T_F64, ddyn(KS2), dconst(nv), dconst(ln), 0, 1, 0, ks, nv, P_F64));
         RK(gemm(T, T_F64, T, T_F64, C, T_F64, ddyn(KS2), ddyn(KS2), dconst(nv), 0, 1, 0, ks, ks, P_F64));
         JacobiDesc d = jac(C, W, ddyn(KS2), ddyn(KS2), bond + 1, mr, st.tol, st.trunc_mode, step);
         d.gram = 1;
         d.total_ext = tot;
         RK(jacobi(d, ks, ks));
-        RK(gemm(W, T_F64, P, T_F64, Qr, T_F64, ddyn(bond + 1), dconst(ln), ddyn(KS2), 0, 0, 0, ks, ln, P_F64));
-        RK(launch_rsvd_accept(dims, bond + 1, at<double>(p.o_ldelta) + step, tot, ks, RSVD_OVERSAMPLE, st.tol,
+        RK(gemm(W, T_F64, Y, T_F64, Qr, T_F64, ddyn(bond + 1), dconst(ln), ddyn(KS2), 0, 0, 0, ks, ln, P_F64));
+        RK(launch_rsvd_accept(dims, bond + 1, at<double>(p.o_ldelta) + step, tot, sig, ks, RSVD_OVERSAMPLE, st.tol,
                               st.trunc_mode, at<int>(p.o_status), flag, s));
         int h = 0;
         RK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
