@@ -212,6 +212,12 @@ int smps_rank_mlp_train(smps_ctx *ctx, int n, const float *feats, const float *l
 int smps_rank_mlp_predict(smps_ctx *ctx, int n, const float *feats, float *out);
 int smps_rank_mlp_get(const smps_ctx *ctx, float *params, int count);
 int smps_rank_mlp_set(smps_ctx *ctx, const float *params, int count);
+/* Training pairs from the last single-problem apply/simplify: for every step
+   whose bond was factorized before in that call, feats (32 floats) are the
+   predictor inputs built from the previous factorization's spectrum and the
+   label is log(kept rank) of this step.  feats: max_pairs x 32, labels:
+   max_pairs (either may be NULL to query *count, the number available). */
+int smps_rank_training_pairs(const smps_ctx *ctx, int max_pairs, float *feats, float *labels, int *count);
 /* One forward + backward of the loss on a host batch, returning the loss and
    the gradient w.r.t. the FP32 master parameters (same order as _get); used to
    check the hand-written backward kernels. */

@@ -32,7 +32,7 @@ EXPORTS = [
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
     "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
-    "smps_rank_mlp_set", "smps_rank_mlp_grad",
+    "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
 ]
 
 
@@ -95,6 +95,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_rank_mlp_predict": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float)]),
         "smps_rank_mlp_get": (c_int, [vp, POINTER(c_float), c_int]),
         "smps_rank_mlp_set": (c_int, [vp, POINTER(c_float), c_int]),
+        "smps_rank_training_pairs": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), ip]),
         "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
                                        POINTER(c_float), c_int]),
     }
@@ -341,6 +342,14 @@ class Context:
     def rank_mlp_set(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
         self._check(self.lib.smps_rank_mlp_set(self.h, _fptr(p), p.size))
+
+    def rank_training_pairs(self):
+        n = c_int()
+        self._check(self.lib.smps_rank_training_pairs(self.h, 0, None, None, byref(n)))
+        f = np.zeros((n.value, 32), dtype=np.float32)
+        y = np.zeros(n.value, dtype=np.float32)
+        self._check(self.lib.smps_rank_training_pairs(self.h, n.value, _fptr(f), _fptr(y), byref(n)))
+        return f, y
 
     def rank_mlp_grad(self, feats, labels):
         f = np.ascontiguousarray(feats, dtype=np.float32)

@@ -13,6 +13,7 @@
 // activations in LDS; each thread owns fixed gradient entries and sums them
 // over the samples in order, so gradients are deterministic.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -365,6 +366,44 @@ int smps_rank_mlp_train(smps_ctx* c, int n, const float* feats, const float* lab
         }
     }
     if (final_loss) *final_loss = last;
+    return SMPS_OK;
+}
+
+int smps_rank_training_pairs(const smps_ctx* c, int max_pairs, float* feats, float* labels, int* count) {
+    if (!c || !count) return SMPS_EINVAL;
+    const int steps = (int)c->log_rank.size();
+    const int L = c->log_L;
+    const int nb = L - 1;
+    if (nb < 1 || steps <= nb || (int)c->log_spec.size() < 32 * steps) {
+        *count = 0;
+        return SMPS_OK;
+    }
+    // step s = 2 nb sw + j: left-to-right bond j (j < nb), else right-to-left bond 2 nb - 1 - j
+    auto prev_step = [&](int s) {
+        const int sw = s / (2 * nb), j = s % (2 * nb);
+        if (j < nb) return (2 * sw - 1) * nb + (nb - 1 - j);  // previous right-to-left visit
+        const int k = 2 * nb - 1 - j;
+        return 2 * sw * nb + k;  // this sweep's left-to-right visit
+    };
+    const int n = steps - nb;
+    *count = n;
+    const int m = std::min(n, std::max(0, max_pairs));
+    for (int i = 0; i < m; ++i) {
+        const int s = nb + i, ps = prev_step(s);
+        const double* sp = c->log_spec.data() + 32 * (size_t)ps;
+        if (feats) {
+            const double s0 = sp[0];
+            for (int j = 0; j < 32; ++j) {
+                double v = std::log(1e-30);
+                if (s0 > 0.0) {
+                    const double r = sp[j] / s0;
+                    if (r > 1e-30) v = std::log(r);
+                }
+                feats[32 * (size_t)i + j] = (float)v;
+            }
+        }
+        if (labels) labels[i] = (float)std::log((double)std::max(1, c->log_rank[s]));
+    }
     return SMPS_OK;
 }
 

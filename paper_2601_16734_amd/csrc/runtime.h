@@ -26,6 +26,7 @@ struct smps_ctx {
     // per step: 0 exact factorization, +k randomized with sketch k accepted,
     // -k randomized with sketch k replaced by the exact one
     std::vector<int> log_fact;
+    int log_L = 0;  // chain length of the logged apply (0 for the batched path)
     // rank predictor state (device buffers, see mlp.hip)
     void* mlp = nullptr;
     // batched execution: captured graph of the last batch shape, and the

@@ -792,6 +792,7 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     c->info.sweeps_done = q.sweeps_done;
     c->info.steps = steps;
     c->log_fact.assign(q.fact_log.begin(), q.fact_log.begin() + std::min<size_t>(steps, q.fact_log.size()));
+    c->log_L = L;
     for (int f : c->log_fact) {
         c->info.rsvd_accepted += f > 0;
         c->info.rsvd_fallbacks += f < 0;
@@ -1252,6 +1253,7 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
     c->info.steps = (int)steps_total;
     c->info.sweeps_done = st.max_sweeps;
     c->log_fact.clear();
+    c->log_L = 0;
     c->log_delta.clear();
     c->log_rank.clear();
     c->log_spec.clear();
