@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle (no parity check, no baseline)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU baseline: repeat the oracle until this much time has passed")
+    ap.add_argument("--a11", action="store_true",
+                    help="only measure the learned-rank randomized factorization (train the predictor on the "
+                         "n=10 / n=20 / L=100 workloads' spectra, evaluate on the L=64 chi=512 decaying-spectrum "
+                         "workload and on a tolerance-bound one) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -80,6 +84,69 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 4}))
 
 
+def learned_rank(args):
+    """Train the rank predictor on the spectra of the exact sweeps of the three
+    exact workloads, then time apply + compression with the exact
+    factorization, the predictor-sized randomized one and the previous-rank-
+    sized one."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+    from paper_2601_16734_amd import rank_training as RT
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    t0 = time.perf_counter()
+    probs = [(w.mpo, w.mps, w.max_bond, w.tol) for w in
+             [synth.workload_laplacian_small(r) for r in range(8)] + [synth.workload_random_mpo(r) for r in range(4)]]
+    F, Y = RT.collect_pairs(ctx, probs, sweeps=4)
+    w3 = synth.workload_xxz(0)
+    F3, Y3 = RT.collect_pairs(ctx, [(w3.mpo, w3.mps, w3.max_bond, w3.tol)], sweeps=1)
+    F, Y = np.concatenate([F, F3]), np.concatenate([Y, Y3])
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = RT.train_predictor(ctx, F, Y, epochs=200)
+    t_train = time.perf_counter() - t0
+    print(f"predictor: {len(Y)} pairs collected in {t_collect:.1f} s, trained in {t_train:.2f} s, "
+          f"loss {loss:.4f}", file=sys.stderr, flush=True)
+
+    def measure(mpo, mps, max_bond, tol, sweeps):
+        U, v = ctx.mpo_create(mpo), ctx.mps_create(mps)
+        res = {}
+        for name, fact in [("exact", B.FACT_SVD), ("predictor", B.FACT_RSVD_MLP), ("previous_rank", B.FACT_RSVD_PREV)]:
+            st = B.strategy(max_bond, tol, sweeps=sweeps, factorization=fact)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out, _ = ctx.mpo_apply(U, v, st)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            info = ctx.last_info()
+            out.destroy()
+            res[name] = {"seconds": dt, "site_updates_per_s": info["steps"] / dt, "norm": info["norm"],
+                         "accepted": info["rsvd_accepted"], "fallbacks": info["rsvd_fallbacks"],
+                         "steps": info["steps"]}
+            print(f"  {name}: {dt:.2f} s, accepted {info['rsvd_accepted']}, fallbacks {info['rsvd_fallbacks']}",
+                  file=sys.stderr, flush=True)
+        for name in ("predictor", "previous_rank"):
+            res[name]["speedup_vs_exact"] = res["exact"]["seconds"] / res[name]["seconds"]
+            res[name]["rel_norm_diff_vs_exact"] = abs(res[name]["norm"] - res["exact"]["norm"]) / res["exact"]["norm"]
+        return res
+
+    out = {"metric": "learned-rank randomized factorization vs exact, apply+compress",
+           "training": {"pairs": int(len(Y)), "loss": loss, "collect_s": t_collect, "train_s": t_train}}
+    rng = np.random.default_rng(31)
+    mps, _ = synth.decaying_spectrum_mps(rng, 32, 2, 256, tau_range=(5.0, 15.0))
+    print("tolerance-bound decaying spectra, L=32 chi=256, identity operator, 2 sweeps", file=sys.stderr)
+    out["tolerance_bound_L32_chi256"] = measure(synth.identity_mpo(32, 2), mps, 256, 1e-10, 2)
+    w5 = synth.workload_decaying(0)
+    print("L=64 chi=512 D=8 decaying spectra, 1 sweep", file=sys.stderr)
+    out["decaying_L64_chi512_D8_1sweep"] = measure(w5.mpo, w5.mps, w5.max_bond, w5.tol, 1)
+    print(json.dumps(out))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -88,6 +155,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.a11:
+        learned_rank(args)
         return
 
     import numpy as np
