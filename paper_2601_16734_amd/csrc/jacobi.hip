@@ -9,20 +9,25 @@
 // orthogonal leaves W = Q diag(s), so the kept rows of Q are W_j / s_j.
 //
 // * jacobi_lds_kernel: the whole matrix resides in LDS (up to ~19k doubles on
-//   gfx950's 160 KB); one workgroup of 1024 threads; disjoint vector pairs of a
-//   round-robin tournament are rotated in parallel, each by a group of lanes
-//   that reduce their three dot products with cross-lane shuffles.
-// * blocked path (larger matrices): the vectors are cut into blocks; in each
-//   round every workgroup takes one pair of blocks into LDS and orthogonalises
-//   the union completely (same device routine), and rounds follow the same
-//   tournament over blocks until a whole sweep changes nothing.
+//   gfx950's 160 KB); one workgroup; a group of 16 lanes (one DPP row) rotates
+//   a pair, reducing its dot product with DPP row moves, and the disjoint
+//   pairs of a round run concurrently (home/away or round-robin ordering).
+// * jacobi_round_kernel (single problem, larger matrices): the rows stay in
+//   global memory; one launch per round of the round-robin tournament, one
+//   wave per pair; the host reads the rotation flag after each sweep.
+// * jacobi_panel_kernel (batched, larger matrices): the vectors are cut into
+//   blocks; in each round every workgroup takes one pair of blocks into LDS
+//   and gives their union one inner sweep; a fixed sweep budget with per-
+//   problem early exit keeps the launch sequence capturable.
 // * select / write: norms, descending order, the truncation rule and the
 //   discarded weight in FP64 (tail summed from the smallest value up), then
 //   the kept rows normalised.
 
 #include <cfloat>
-#include <cstdio>
-#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -34,6 +39,9 @@ constexpr int JT = 1024;               // threads per Jacobi workgroup (blocked 
 __host__ __device__ constexpr int lds_threads(int E) { return E >= 16 ? 512 : 1024; }
 constexpr int LDS_BYTES = 160 * 1024;  // gfx950 LDS per workgroup
 constexpr int JAC_MAX_SWEEPS = 40;
+// cold starts of large, strongly graded matrices need many round-robin sweeps
+// (two-site tensors with singular values spread over 13 decades take ~40)
+constexpr int ROUND_MAX_SWEEPS = 120;
 constexpr int SEL_MAX = 2048;          // vectors handled by the select kernel
 
 __device__ __forceinline__ int tourney(int pos, int rd, int n2) {
@@ -542,6 +550,65 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const J
     if (tid == 0 && d.conv) atomicOr(d.conv, 1);
 }
 
+// One round of the global-memory path for matrices too large for LDS: wave w
+// of workgroup b takes pair 4 b + w of round rd of the round-robin tournament,
+// reads both rows (EW elements per lane, len <= 64 EW), forms the three dot
+// products, rotates and writes the rows back.  A launch per round is the
+// only synchronisation; the host reads the rotation flag after each sweep.
+template <int EW>
+__global__ __launch_bounds__(256) void jacobi_round_kernel(JacobiDesc d, int rd) {
+    const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
+    const int P = (nv + 1) / 2, n2 = 2 * P;
+    const int lane = threadIdx.x & 63;
+    const int pi = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (pi >= P || rd >= n2 - 1) return;  // wave-uniform
+    const int p = tourney(pi, rd, n2), q = tourney(n2 - 1 - pi, rd, n2);
+    if (p >= nv || q >= nv) return;
+    double* wp = d.X + (size_t)p * len;
+    double* wq = d.X + (size_t)q * len;
+    double x[EW], y[EW];
+    double a0 = 0.0, b0 = 0.0, c0 = 0.0;
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+        const int i = lane + 64 * e;
+        x[e] = i < len ? wp[i] : 0.0;
+        y[e] = i < len ? wq[i] : 0.0;
+        a0 = fma(x[e], x[e], a0);
+        b0 = fma(y[e], y[e], b0);
+        c0 = fma(x[e], y[e], c0);
+    }
+    a0 = row_sum16(a0);
+    b0 = row_sum16(b0);
+    c0 = row_sum16(c0);
+    a0 += __shfl_xor(a0, 16, 64);
+    b0 += __shfl_xor(b0, 16, 64);
+    c0 += __shfl_xor(c0, 16, 64);
+    a0 += __shfl_xor(a0, 32, 64);
+    b0 += __shfl_xor(b0, 32, 64);
+    c0 += __shfl_xor(c0, 32, 64);
+    if (!isfinite(a0) || !isfinite(b0)) {
+        if (lane == 0 && d.status) atomicOr(d.status, 1);
+        return;
+    }
+    const double tiny = fmax(DBL_MIN * 1.0e4, zero_floor2(*d.fro2, nv, len, d.floor_eps));
+    if (!(a0 > tiny && b0 > tiny)) return;
+    const double tol = DBL_EPSILON * (double)(len > 16 ? len : 16);
+    if (!jacobi_needs_rotation(a0, b0, c0, tol)) return;
+    double cs, sn, t;
+    jacobi_rotation(a0, b0, c0, cs, sn, t);
+#pragma unroll
+    for (int e = 0; e < EW; ++e) {
+        const int i = lane + 64 * e;
+        if (i < len) {
+            wp[i] = cs * x[e] - sn * y[e];
+            wq[i] = sn * x[e] + cs * y[e];
+        }
+    }
+    if (lane == 0) atomicOr(d.conv, 1);
+}
+
+__global__ void or_int_kernel(int* p, int v) { atomicOr(p, v); }
+
 // Blocked path finish: select on the vectors in global memory.
 __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const JacobiDesc* arr) {
     const JacobiDesc d = arr ? arr[blockIdx.x] : d0;
@@ -551,7 +618,7 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const 
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     jacobi_select(d.X, nv, len, len, sig_raw, sig_sorted, perm_s, d, &s_delta);
-    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // blocked sweeps are not counted per step
+    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // sweeps of the global-memory paths are not logged
     for (int j = threadIdx.x; j < nv; j += JT) d.perm[j] = perm_s[j];
 }
 
@@ -689,6 +756,89 @@ static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, in
     }
 }
 
+// One sweep of the global-memory path (flag reset + one launch per round) as
+// a HIP graph, captured once per (device, operands, sizes) and replayed: the
+// sweep is hundreds of tiny launches, and replaying them from a graph costs a
+// fraction of issuing them one by one.
+namespace {
+struct SweepGraphs {
+    std::mutex m;
+    std::unordered_map<std::string, hipGraphExec_t> exec;
+};
+SweepGraphs& sweep_graphs() {
+    static SweepGraphs g;
+    return g;
+}
+template <typename T>
+void key_add(std::string& k, const T& v) {
+    k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+}  // namespace
+
+static void enqueue_round_sweep(const JacobiDesc& dd, int rounds, int ew, dim3 grid, int* flags, hipStream_t s) {
+    const dim3 block(256);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
+    for (int rd = 0; rd < rounds; ++rd) {
+        switch (ew) {
+            case 2: hipLaunchKernelGGL(jacobi_round_kernel<2>, grid, block, 0, s, dd, rd); break;
+            case 4: hipLaunchKernelGGL(jacobi_round_kernel<4>, grid, block, 0, s, dd, rd); break;
+            case 8: hipLaunchKernelGGL(jacobi_round_kernel<8>, grid, block, 0, s, dd, rd); break;
+            case 16: hipLaunchKernelGGL(jacobi_round_kernel<16>, grid, block, 0, s, dd, rd); break;
+            default: hipLaunchKernelGGL(jacobi_round_kernel<32>, grid, block, 0, s, dd, rd); break;
+        }
+    }
+}
+
+static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, dim3 grid, int* flags,
+                                    hipGraphExec_t* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::string key;
+    key_add(key, dev);
+    key_add(key, dd.X);
+    key_add(key, dd.dims_in);
+    key_add(key, dd.nvec);
+    key_add(key, dd.len);
+    key_add(key, dd.status);
+    key_add(key, dd.fro2);
+    key_add(key, dd.floor_eps);
+    key_add(key, flags);
+    key_add(key, rounds);
+    key_add(key, ew);
+    key_add(key, grid.x);
+    SweepGraphs& sg = sweep_graphs();
+    std::lock_guard<std::mutex> lock(sg.m);
+    auto it = sg.exec.find(key);
+    if (it != sg.exec.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    if (sg.exec.size() >= 4096) {  // bounded: drop everything and start again
+        for (auto& kv : sg.exec) hipGraphExecDestroy(kv.second);
+        sg.exec.clear();
+    }
+    hipStream_t cs;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue_round_sweep(dd, rounds, ew, grid, flags, cs);
+        e = hipGetLastError();
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) return e;
+    sg.exec.emplace(std::move(key), exec);
+    *out = exec;
+    return hipSuccess;
+}
+
 hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
     (void)work;
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
@@ -697,30 +847,36 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
         return hipGetLastError();
     }
     if (nvec_cap > SEL_MAX) return hipErrorInvalidValue;
-    // blocked path; `flags` is one device int used as the "rotated" flag, and
-    // the host reads it after every sweep
+    if (len_cap > 64 * 32) return hipErrorInvalidValue;
+    // global-memory path: one launch per round of the tournament; `flags` is
+    // one device int used as the "rotated" flag, read by the host after every sweep
     JacobiDesc dd = d;
-    jacobi_panel_params(nvec_cap, len_cap, &dd.bs, &dd.nblk);
     dd.conv = flags;
     dd.done = nullptr;
     if (!dd.fro2) return hipErrorInvalidValue;
-    const size_t shm = sizeof(double) * 2 * (size_t)dd.bs * len_cap;
     hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
+    const int P = (nvec_cap + 1) / 2, rounds = 2 * P - 1;
+    const dim3 grid((P + 3) / 4);
+    const int ew = len_cap <= 128 ? 2 : len_cap <= 256 ? 4 : len_cap <= 512 ? 8 : len_cap <= 1024 ? 16 : 32;
+    hipGraphExec_t exec = nullptr;
+    hipError_t ge = round_sweep_graph(dd, rounds, ew, grid, flags, &exec);
+    if (ge != hipSuccess) return ge;
     int sweep = 0;
-    for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
-        hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
-        for (int rd = 0; rd < dd.nblk - 1; ++rd)
-            hipLaunchKernelGGL(jacobi_panel_kernel, dim3(dd.nblk / 2, 1), dim3(JT), shm, s, dd, nullptr, rd);
+    bool converged = false;
+    for (; sweep < ROUND_MAX_SWEEPS; ++sweep) {
+        hipError_t e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) return e;
         int h = 0;
-        hipError_t e = hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(&h, flags, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        if (!h) break;
+        if (!h) {
+            converged = true;
+            break;
+        }
     }
-    static const bool dbg = getenv("SMPS_DEBUG_BLOCKED") != nullptr;
-    if (dbg) fprintf(stderr, "blocked jacobi: nvec_cap %d len_cap %d bs %d nblk %d sweeps %d\n", nvec_cap, len_cap,
-                     dd.bs, dd.nblk, sweep + 1);
+    if (!converged && dd.status) hipLaunchKernelGGL(or_int_kernel, dim3(1), dim3(1), 0, s, dd.status, 2);
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
     const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
