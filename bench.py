@@ -209,8 +209,11 @@ def main():
 
     results = {}
     stream = torch.cuda.current_stream()
+    tuned = {}
     for prec in args.precisions.split(","):
         st = B.strategy(w.max_bond, w.tol, sweeps=w.sweeps, precision=prec)
+        # GEMM tile autotuning for this workload's product shapes (setup, untimed)
+        tuned[prec] = ctx.autotune_apply(U, v, st, reps=5)
         for _ in range(args.warmup):
             out, _ = ctx.mpo_apply(U, v, st)
             out.destroy()
@@ -273,7 +276,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64", "bf16": "bf16+f64"}[best_p],
         "data": "synthetic",
         "config": {"workload": "random MPO D=8 on random MPS n=20 d=2 chi=64, max bond 64, tol 1e-10, 4 sweeps",
-                   "site_updates_per_step": site_updates, "precision": best_p},
+                   "site_updates_per_step": site_updates, "precision": best_p,
+                   "gemm_shapes_autotuned": tuned.get(best_p)},
         "fp64_site_updates_per_s": fp64["site_updates_per_s"] if fp64 else None,
         "speedup_vs_fp64": (best["site_updates_per_s"] / fp64["site_updates_per_s"]) if fp64 else None,
         "per_precision": results,

@@ -224,6 +224,29 @@ int smps_rank_training_pairs(const smps_ctx *ctx, int max_pairs, float *feats, f
 int smps_rank_mlp_grad(smps_ctx *ctx, int n, const float *feats, const float *labels, float *loss,
                        float *grad, int count);
 
+/* ---- GEMM tile autotuner --------------------------------------------------------
+ * Each dense product runs with one of four output tiles (64x64, 64x32, 32x64,
+ * 32x32, ids 0-3).  The process-wide table maps (precision, operand/result
+ * types, transposes, power-of-two buckets of the M and N allocation caps) to
+ * the fastest tile; products without an entry use 64x64.  The tile never
+ * changes result bits (every tile sums each output in the same k order).
+ *   smps_autotune_apply: record the products one apply + compression of
+ *       (U, v, strategy) would launch, time the four tiles on each distinct
+ *       shape (reps launches each, synthetic operands) and store the best;
+ *       *tuned (nullable) receives the number of shapes timed.
+ *   smps_autotune_gemm: the same for one M x N x K product (types SMPS_F64 /
+ *       SMPS_F32, ta/tb/tc as in the library's products); *best_tile nullable.
+ *   smps_autotune_save / _load: the table as JSON (one entry per line; load
+ *       merges); smps_autotune_clear empties it; smps_autotune_entries counts. */
+int smps_autotune_apply(smps_ctx *ctx, const smps_mpo *U, const smps_mps *v, const smps_strategy *strategy,
+                        int reps, int *tuned);
+int smps_autotune_gemm(smps_ctx *ctx, int precision, int M, int N, int K, int ta, int tb, int tc, int a_type,
+                       int b_type, int c_type, int reps, int *best_tile);
+int smps_autotune_save(smps_ctx *ctx, const char *path);
+int smps_autotune_load(smps_ctx *ctx, const char *path);
+int smps_autotune_clear(smps_ctx *ctx);
+int smps_autotune_entries(const smps_ctx *ctx, int *count);
+
 #ifdef __cplusplus
 }
 #endif

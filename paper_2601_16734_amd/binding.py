@@ -33,6 +33,8 @@ EXPORTS = [
     "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
+    "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
+    "smps_autotune_entries",
 ]
 
 
@@ -96,6 +98,13 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_rank_mlp_get": (c_int, [vp, POINTER(c_float), c_int]),
         "smps_rank_mlp_set": (c_int, [vp, POINTER(c_float), c_int]),
         "smps_rank_training_pairs": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), ip]),
+        "smps_autotune_apply": (c_int, [vp, vp, vp, POINTER(Strategy), c_int, ip]),
+        "smps_autotune_gemm": (c_int, [vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int,
+                                       c_int, ip]),
+        "smps_autotune_save": (c_int, [vp, ctypes.c_char_p]),
+        "smps_autotune_load": (c_int, [vp, ctypes.c_char_p]),
+        "smps_autotune_clear": (c_int, [vp]),
+        "smps_autotune_entries": (c_int, [vp, ip]),
         "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
                                        POINTER(c_float), c_int]),
     }
@@ -342,6 +351,33 @@ class Context:
     def rank_mlp_set(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)
         self._check(self.lib.smps_rank_mlp_set(self.h, _fptr(p), p.size))
+
+    # ---- GEMM tile autotuner
+    def autotune_apply(self, U: "MPO", v: "MPS", st: Strategy, reps: int = 5) -> int:
+        n = c_int()
+        self._check(self.lib.smps_autotune_apply(self.h, U.h, v.h, byref(st), int(reps), byref(n)))
+        return n.value
+
+    def autotune_gemm(self, precision, M, N, K, ta=0, tb=0, tc=0, a_type=0, b_type=0, c_type=0, reps=5) -> int:
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        best = c_int()
+        self._check(self.lib.smps_autotune_gemm(self.h, prec, M, N, K, ta, tb, tc, a_type, b_type, c_type, reps,
+                                                byref(best)))
+        return best.value
+
+    def autotune_save(self, path: str):
+        self._check(self.lib.smps_autotune_save(self.h, str(path).encode()))
+
+    def autotune_load(self, path: str):
+        self._check(self.lib.smps_autotune_load(self.h, str(path).encode()))
+
+    def autotune_clear(self):
+        self._check(self.lib.smps_autotune_clear(self.h))
+
+    def autotune_entries(self) -> int:
+        n = c_int()
+        self._check(self.lib.smps_autotune_entries(self.h, byref(n)))
+        return n.value
 
     def rank_training_pairs(self):
         n = c_int()

@@ -432,6 +432,17 @@ int smps_last_log(const smps_ctx* c, int max_steps, double* deltas, int* ranks, 
     return SMPS_OK;
 }
 
+int smps_autotune_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy* st, int reps,
+                        int* tuned) {
+    if (!c) return SMPS_EINVAL;
+    if (!U || !v) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_strategy(c, st);
+    if (rc != SMPS_OK) return rc;
+    if (reps < 1) return fail(c, SMPS_EINVAL, "reps must be >= 1");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    return run_autotune(c, U, v, *st, reps, tuned);
+}
+
 int smps_last_factor_log(const smps_ctx* c, int max_steps, int* kinds, int* steps) {
     if (!c) return SMPS_EINVAL;
     const int n = (int)c->log_fact.size();

@@ -104,6 +104,14 @@ struct JacobiDesc {
 // ---- host-side launch helpers (defined in the kernel translation units) ----
 namespace smps {
 hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec);
+// GEMM output tiles: 0 = 64 x 64, 1 = 64 x 32, 2 = 32 x 64, 3 = 32 x 32
+constexpr int GEMM_TILES = 4;
+__host__ __device__ constexpr int gemm_tile_m(int t) { return t == 2 || t == 3 ? 32 : 64; }
+__host__ __device__ constexpr int gemm_tile_n(int t) { return t == 1 || t == 3 ? 32 : 64; }
+hipError_t launch_gemm_tile(const GemmDesc& g, const GemmDesc* arr, int M_cap, int N_cap, int count, hipStream_t s,
+                            int prec, int tile);
+// tile from the autotuner's table for this product shape (64 x 64 without an entry)
+int gemm_tile_for(const GemmDesc& g, int M_cap, int N_cap, int prec);
 hipError_t launch_left_mpo(const LeftMpoDesc& d, int a_cap, hipStream_t s);
 hipError_t launch_right_mpo(const RightMpoDesc& d, int c_cap, hipStream_t s);
 // Exact factorization.  Chooses the LDS-resident kernel when nvec_cap*len_cap

@@ -12,8 +12,11 @@
 // (x = hi + lo, product hi*hi + hi*lo + lo*hi, all with FP32 accumulation).
 // Operands are converted from their storage type while being staged in LDS.
 //
-// Workgroup: 256 threads = 4 wave64s arranged 2 x 2, tile 64 x 64, each wave
-// owning a 32 x 32 block of 2 x 2 MFMA 16 x 16 outputs.
+// Workgroup: 256 threads = 4 wave64s arranged 2 x 2 over a TM x TN output
+// tile (TM, TN in {32, 64}); each wave owns a (TM/2) x (TN/2) block of
+// 16 x 16 MFMA outputs.  Small products (few tiles) run faster on the smaller
+// tiles, larger ones on 64 x 64; the tile of each product shape is chosen by
+// the autotuner (autotune.hip) when a table entry exists, else 64 x 64.
 
 #include "common.h"
 
@@ -23,7 +26,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64;
 
 template <typename T>
 __device__ __forceinline__ double ldg(const void* p, size_t i) {
@@ -51,7 +53,7 @@ __device__ __forceinline__ double opA(const void* A, int ta, int M, int K, int r
 // ---------------------------------------------------------------------------
 // FP64 / FP32 path: BK = 16, LDS holds A as [k][m] and B as [k][n].
 // ---------------------------------------------------------------------------
-template <int PREC, typename TA, typename TB, typename TC>
+template <int PREC, typename TA, typename TB, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc* garr) {
     // one descriptor, or one per blockIdx.z (batched launch over independent problems)
     const GemmDesc g = garr ? garr[blockIdx.z] : g0;
@@ -66,14 +68,15 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
 
     __shared__ CT As[BK][BM + 4];
     __shared__ CT Bs[BK][BN + 4];
+    constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 fragments per wave
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
 
     typedef typename std::conditional<PREC == P_F64, v4d, v4f>::type acc_t;
-    acc_t acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    acc_t acc[FM][FN];
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
     for (int k0 = 0; k0 < K; k0 += BK) {
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         for (int e0 = 0; e0 < BM * BK; e0 += 256) {
             const int e = e0 + tid;
             int mm, kk;
-            if (!g.ta) { mm = e >> 4; kk = e & 15; } else { kk = e >> 6; mm = e & 63; }
+            if (!g.ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
             const int gm = m0 + mm, gk = k0 + kk;
             CT v = 0;
             if (gm < M && gk < K) v = (CT)opA<TA>(A, g.ta, M, K, gm, gk);
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         for (int e0 = 0; e0 < BN * BK; e0 += 256) {
             const int e = e0 + tid;
             int nn, kk;
-            if (!g.tb) { kk = e >> 6; nn = e & 63; } else { nn = e >> 4; kk = e & 15; }
+            if (!g.tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
             const int gn = n0 + nn, gk = k0 + kk;
             CT v = 0;
             if (gn < N && gk < K)
@@ -101,11 +104,11 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            CT a[2], b[2];
-            for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm + i * 16 + li];
-            for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lk][wn + j * 16 + li];
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j) {
+            CT a[FM], b[FN];
+            for (int i = 0; i < FM; ++i) a[i] = As[kk + lk][wm + i * 16 + li];
+            for (int j = 0; j < FN; ++j) b[j] = Bs[kk + lk][wn + j * 16 + li];
+            for (int i = 0; i < FM; ++i)
+                for (int j = 0; j < FN; ++j) {
                     if constexpr (PREC == P_F64)
                         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
                     else
@@ -115,8 +118,8 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         __syncthreads();
     }
     const CT alpha = (CT)g.alpha;
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) {
                 // v_mfma_f64_16x16x4 returns rows lk + 4v; the f32 forms return rows 4lk + v
                 const int row = m0 + wm + i * 16 + (PREC == P_F64 ? lk + 4 * v : lk * 4 + v);
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
 // BF16 / BF16x3 path: BK = 32, LDS holds A as [m][k] and B as [n][k] so that a
 // lane's eight consecutive k values are one 16-byte read.
 // ---------------------------------------------------------------------------
-template <int PREC, typename TA, typename TB, typename TC>
+template <int PREC, typename TA, typename TB, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDesc* garr) {
     // one descriptor, or one per blockIdx.z (batched launch over independent problems)
     const GemmDesc g = garr ? garr[blockIdx.z] : g0;
@@ -149,13 +152,14 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
     __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LD];
     __shared__ __attribute__((aligned(16))) unsigned short Al[SPLIT ? BM : 1][LD];
     __shared__ __attribute__((aligned(16))) unsigned short Bl[SPLIT ? BN : 1][LD];
+    constexpr int FM = BM / 32, FN = BN / 32;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
     const int li = lane & 15, lk = lane >> 4;
 
-    v4f acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    v4f acc[FM][FN];
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.f;
 
     for (int k0 = 0; k0 < K; k0 += BK) {
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         for (int e0 = 0; e0 < BM * BK; e0 += 256) {
             const int e = e0 + tid;
             int mm, kk;
-            if (!g.ta) { mm = e >> 5; kk = e & 31; } else { kk = e >> 6; mm = e & 63; }
+            if (!g.ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
             const int gm = m0 + mm, gk = k0 + kk;
             float v = 0.f;
             if (gm < M && gk < K) v = (float)opA<TA>(A, g.ta, M, K, gm, gk);
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         for (int e0 = 0; e0 < BN * BK; e0 += 256) {
             const int e = e0 + tid;
             int nn, kk;
-            if (!g.tb) { kk = e >> 6; nn = e & 63; } else { nn = e >> 5; kk = e & 31; }
+            if (!g.tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
             const int gn = n0 + nn, gk = k0 + kk;
             float v = 0.f;
             if (gn < N && gk < K)
@@ -185,17 +189,17 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
             if constexpr (SPLIT) Bl[nn][kk] = f2bf(v - bf2f(h));
         }
         __syncthreads();
-        v8bf ah[2], bh[2], al[2], bl[2];
-        for (int i = 0; i < 2; ++i) {
+        v8bf ah[FM], bh[FN], al[FM], bl[FN];
+        for (int i = 0; i < FM; ++i) {
             ah[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Ah[wm + i * 16 + li][lk * 8]);
             if constexpr (SPLIT) al[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Al[wm + i * 16 + li][lk * 8]);
         }
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < FN; ++j) {
             bh[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bh[wn + j * 16 + li][lk * 8]);
             if constexpr (SPLIT) bl[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bl[wn + j * 16 + li][lk * 8]);
         }
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
+        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j) {
                 if constexpr (SPLIT) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
@@ -205,8 +209,8 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         __syncthreads();
     }
     const float alpha = (float)g.alpha;
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm + i * 16 + lk * 4 + v;
                 const int col = n0 + wn + j * 16 + li;
@@ -217,40 +221,57 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
             }
 }
 
-template <int PREC, typename TA, typename TB, typename TC>
+template <int PREC, typename TA, typename TB, typename TC, int BM, int BN>
 static void launch_t(const GemmDesc& g, const GemmDesc* arr, dim3 grid, hipStream_t s) {
     if constexpr (PREC == P_F64 || PREC == P_F32)
-        hipLaunchKernelGGL((gemm_kernel_f<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g, arr);
+        hipLaunchKernelGGL((gemm_kernel_f<PREC, TA, TB, TC, BM, BN>), grid, dim3(256), 0, s, g, arr);
     else
-        hipLaunchKernelGGL((gemm_kernel_bf<PREC, TA, TB, TC>), grid, dim3(256), 0, s, g, arr);
+        hipLaunchKernelGGL((gemm_kernel_bf<PREC, TA, TB, TC, BM, BN>), grid, dim3(256), 0, s, g, arr);
+}
+
+template <int PREC, int BM, int BN>
+static void launch_types(const GemmDesc& g, const GemmDesc* arr, dim3 grid, hipStream_t s) {
+    const int code = (g.a_type << 2) | (g.b_type << 1) | g.c_type;
+    switch (code) {
+        case 0: launch_t<PREC, double, double, double, BM, BN>(g, arr, grid, s); break;
+        case 1: launch_t<PREC, double, double, float, BM, BN>(g, arr, grid, s); break;
+        case 2: launch_t<PREC, double, float, double, BM, BN>(g, arr, grid, s); break;
+        case 3: launch_t<PREC, double, float, float, BM, BN>(g, arr, grid, s); break;
+        case 4: launch_t<PREC, float, double, double, BM, BN>(g, arr, grid, s); break;
+        case 5: launch_t<PREC, float, double, float, BM, BN>(g, arr, grid, s); break;
+        case 6: launch_t<PREC, float, float, double, BM, BN>(g, arr, grid, s); break;
+        default: launch_t<PREC, float, float, float, BM, BN>(g, arr, grid, s); break;
+    }
 }
 
 template <int PREC>
-static void launch_prec(const GemmDesc& g, const GemmDesc* arr, dim3 grid, hipStream_t s) {
-    const int code = (g.a_type << 2) | (g.b_type << 1) | g.c_type;
-    switch (code) {
-        case 0: launch_t<PREC, double, double, double>(g, arr, grid, s); break;
-        case 1: launch_t<PREC, double, double, float>(g, arr, grid, s); break;
-        case 2: launch_t<PREC, double, float, double>(g, arr, grid, s); break;
-        case 3: launch_t<PREC, double, float, float>(g, arr, grid, s); break;
-        case 4: launch_t<PREC, float, double, double>(g, arr, grid, s); break;
-        case 5: launch_t<PREC, float, double, float>(g, arr, grid, s); break;
-        case 6: launch_t<PREC, float, float, double>(g, arr, grid, s); break;
-        default: launch_t<PREC, float, float, float>(g, arr, grid, s); break;
+static void launch_prec(const GemmDesc& g, const GemmDesc* arr, int tile, int M_cap, int N_cap, int count,
+                        hipStream_t s) {
+    const int bm = gemm_tile_m(tile), bn = gemm_tile_n(tile);
+    const dim3 grid((N_cap + bn - 1) / bn, (M_cap + bm - 1) / bm, count);
+    switch (tile) {
+        case 1: launch_types<PREC, 64, 32>(g, arr, grid, s); break;
+        case 2: launch_types<PREC, 32, 64>(g, arr, grid, s); break;
+        case 3: launch_types<PREC, 32, 32>(g, arr, grid, s); break;
+        default: launch_types<PREC, 64, 64>(g, arr, grid, s); break;
     }
+}
+
+hipError_t launch_gemm_tile(const GemmDesc& g, const GemmDesc* arr, int M_cap, int N_cap, int count, hipStream_t s,
+                            int prec, int tile) {
+    if (M_cap <= 0 || N_cap <= 0 || count <= 0) return hipSuccess;
+    switch (prec) {
+        case P_F64: launch_prec<P_F64>(g, arr, tile, M_cap, N_cap, count, s); break;
+        case P_F32: launch_prec<P_F32>(g, arr, tile, M_cap, N_cap, count, s); break;
+        case P_BF16X3: launch_prec<P_BF16X3>(g, arr, tile, M_cap, N_cap, count, s); break;
+        default: launch_prec<P_BF16>(g, arr, tile, M_cap, N_cap, count, s); break;
+    }
+    return hipGetLastError();
 }
 
 static hipError_t launch_any(const GemmDesc& g, const GemmDesc* arr, int M_cap, int N_cap, int count, hipStream_t s,
                              int prec) {
-    if (M_cap <= 0 || N_cap <= 0 || count <= 0) return hipSuccess;
-    dim3 grid((N_cap + BN - 1) / BN, (M_cap + BM - 1) / BM, count);
-    switch (prec) {
-        case P_F64: launch_prec<P_F64>(g, arr, grid, s); break;
-        case P_F32: launch_prec<P_F32>(g, arr, grid, s); break;
-        case P_BF16X3: launch_prec<P_BF16X3>(g, arr, grid, s); break;
-        default: launch_prec<P_BF16>(g, arr, grid, s); break;
-    }
-    return hipGetLastError();
+    return launch_gemm_tile(g, arr, M_cap, N_cap, count, s, prec, gemm_tile_for(g, M_cap, N_cap, prec));
 }
 
 hipError_t launch_gemm(const GemmDesc& g, int M_cap, int N_cap, int batch, hipStream_t s, int prec) {

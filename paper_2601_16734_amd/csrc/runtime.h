@@ -87,6 +87,10 @@ struct ApplyProblem {
 int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
               double* trunc_err);
 void mlp_free(smps_ctx* c);
+// GEMM tile autotuning (autotune.hip / sweep.hip)
+int tune_gemm_shape(smps_ctx* c, int prec, int a_type, int b_type, int c_type, int ta, int tb, int tc, int M, int N,
+                    int K, int reps, int* best_out);
+int run_autotune(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, int reps, int* tuned);
 // rank predictor: log-rank predictions for n device feature rows (32 floats each)
 hipError_t mlp_predict_device(smps_ctx* c, const float* feats_dev, int n, float* out_dev, hipStream_t s);
 bool mlp_ready(const smps_ctx* c);

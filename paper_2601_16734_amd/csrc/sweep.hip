@@ -17,6 +17,8 @@
 // one environment.
 
 #include <algorithm>
+#include <set>
+#include <tuple>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -821,6 +823,42 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
     if (e != hipSuccess)
         return fail(c, SMPS_EHIP, std::string("enqueue failed at ") + q.where + ": " + hipGetErrorString(e));
     return finish(c, p, q, st, out, trunc_err);
+}
+
+// Autotune every product shape one apply + compression would launch: the
+// sequence is recorded (nothing runs), each GEMM's extents are evaluated at
+// the allocation caps, and each distinct table key is timed once.
+int run_autotune(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, int reps,
+                 int* tuned) {
+    Plan p;
+    Layout lay;
+    plan_problem(p, U, v, st, lay);
+    std::vector<Op> ops;
+    Enq q{p, U, v, st, nullptr, c->stream, nullptr};
+    q.rec = &ops;
+    hipError_t e = q.run();
+    if (e != hipSuccess) return fail(c, SMPS_EHIP, std::string("autotune: recording failed at ") + q.where);
+    const int L = p.L;
+    const int cap_max = *std::max_element(p.capb.begin(), p.capb.end());
+    auto cap_of = [&](DimExpr x) { return x.idx < 0 ? x.mul : x.mul * (x.idx <= L ? p.capb[x.idx] : cap_max); };
+    std::set<std::tuple<int, int, int, int, int, int, int, int, int>> seen;
+    int n = 0;
+    for (const Op& op : ops) {
+        if (op.kind != OP_GEMM) continue;
+        const GemmDesc& g = op.g;
+        const int M = op.cap0, N = op.cap1, K = cap_of(g.K);
+        if (M < 1 || N < 1 || K < 1) continue;
+        int bm = 1, bn = 1;
+        while (bm < M) bm <<= 1;
+        while (bn < N) bn <<= 1;
+        if (!seen.insert({op.prec, g.a_type, g.b_type, g.c_type, g.ta, g.tb, g.tc, bm, bn}).second) continue;
+        int best = 0;
+        const int rc = tune_gemm_shape(c, op.prec, g.a_type, g.b_type, g.c_type, g.ta, g.tb, g.tc, M, N, K, reps, &best);
+        if (rc != SMPS_OK) return rc;
+        ++n;
+    }
+    if (tuned) *tuned = n;
+    return SMPS_OK;
 }
 
 // ---------------------------------------------------------------------------
