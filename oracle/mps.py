@@ -174,6 +174,7 @@ class SweepResult:
     deltas: list = field(default_factory=list)     # discarded weight per step
     norms2: list = field(default_factory=list)     # ||psi||^2 after each step
     spectra: list = field(default_factory=list)    # (sweep, direction, bond, s)
+    step_ranks: list = field(default_factory=list)  # kept rank of each step
     error_bound: float = 0.0
 
     @property
@@ -197,7 +198,7 @@ def _split(theta, a, s, t, c, tol, max_bond, mode, direction):
 
 
 def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
-                   mode: int = REL_NORM2, guess=None, split_hook=None) -> SweepResult:
+                   mode: int = REL_NORM2, guess=None, split_hook=None, max_steps=None) -> SweepResult:
     """Route F: compress U v with three-layer environments <psi | U | v>.
 
     L[k][a, b, x] contracts sites < k of psi (a), U (b) and v (x);
@@ -212,6 +213,9 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
     as split_hook(theta, bond, direction, sweep, step, previous) with previous
     = (spectrum, kept rank) of the bond's last split, or None, and returns
     None (exact split) or (left, right, r, delta, s).
+
+    max_steps (optional) stops after that many two-site steps, leaving the
+    per-step log of those steps (the state is then not a finished result).
     """
     L = len(mps)
     A = [np.asarray(x, dtype=np.float64) for x in mps]
@@ -259,10 +263,15 @@ def apply_simplify(mpo, mps, max_bond: int, tol: float, sweeps: int = 4,
                 left, right, r, delta, S = got
                 last_spectrum[k] = (S, r)
                 step += 1
+                res.step_ranks.append(r)
                 psi[k], psi[k + 1] = left, right
                 res.deltas.append(delta)
                 res.norms2.append(float(np.sum(S[:r] ** 2)))
                 res.spectra.append((sw, direction, k, S))
+                if max_steps is not None and step >= max_steps:
+                    res.mps = psi
+                    res.norm = float("nan")
+                    return res
                 if direction > 0:
                     Lenv[k + 1] = grow_left(Lenv[k], psi[k], B[k], A[k])
                 else:
