@@ -135,12 +135,14 @@ class MPS:
         self.h = handle
 
     def shape(self):
+        if not self.h:
+            raise SmpsError(EINVAL, "MPS handle was destroyed")
         L = c_int()
-        self.ctx.lib.smps_mps_shape(self.h, byref(L), None, None, None)
+        self.ctx._check(self.ctx.lib.smps_mps_shape(self.h, byref(L), None, None, None))
         phys = (c_int * L.value)()
         bonds = (c_int * (L.value + 1))()
         center = c_int()
-        self.ctx.lib.smps_mps_shape(self.h, None, phys, bonds, byref(center))
+        self.ctx._check(self.ctx.lib.smps_mps_shape(self.h, None, phys, bonds, byref(center)))
         return list(phys), list(bonds), center.value
 
     def read(self) -> list[np.ndarray]:

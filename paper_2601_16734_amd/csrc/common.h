@@ -125,6 +125,7 @@ int jacobi_lds_limit();
 int jacobi_lds_class(int len_cap);
 size_t jacobi_lds_bytes(int nvec_cap, int len_cap);
 void jacobi_panel_params(int nvec_cap, int len_cap, int* bs, int* nblk);
+size_t jacobi_panel_bytes(int len_cap, int bs);
 hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s);
 hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk, int max_rows,
                                        int len_cap, size_t shm, int sweeps, hipStream_t s);

@@ -503,7 +503,9 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
 // tournament position i, orthogonalises the union in LDS, writes it back.
 // Batched launches index the factorization by blockIdx.y; a factorization
 // whose `done` flag is set (converged in an earlier sweep) exits at once.
-__global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr, int rd) {
+template <int E>
+__global__ __launch_bounds__(lds_threads(E)) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr, int rd) {
+    constexpr int NT = lds_threads(E);
     extern __shared__ double sm[];
     __shared__ int s_flag, s_bad;
     __shared__ double s_nrm[64];
@@ -512,6 +514,8 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const J
     if (rd >= nblk2 - 1 || (int)blockIdx.x >= nblk2 / 2) return;
     if (d.done && *d.done) return;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
+    // rows zero padded to 16 E in LDS for the register path (E > 0)
+    const int ld = E > 0 ? 16 * E : len;
     const int bp = tourney(blockIdx.x, rd, nblk2), bq = tourney(nblk2 - 1 - blockIdx.x, rd, nblk2);
     // vectors of the two blocks that exist
     int idx[2], cnt[2];
@@ -525,11 +529,14 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const J
     if (tid == 0) s_bad = 0;
     __syncthreads();
     int bad = 0;
-    for (size_t e = tid; e < (size_t)nloc * len; e += JT) {
-        const int j = (int)(e / len), l = (int)(e % len);
+    for (size_t e = tid; e < (size_t)nloc * ld; e += NT) {
+        const int j = (int)(e / ld), l = (int)(e % ld);
         const int gj = j < cnt[0] ? idx[0] + j : idx[1] + (j - cnt[0]);
-        const double x = d.X[(size_t)gj * len + l];
-        bad |= !isfinite(x);
+        double x = 0.0;
+        if (l < len) {
+            x = d.X[(size_t)gj * len + l];
+            bad |= !isfinite(x);
+        }
         sm[e] = x;
     }
     if (bad) s_bad = 1;
@@ -539,11 +546,12 @@ __global__ __launch_bounds__(JT) void jacobi_panel_kernel(JacobiDesc d0, const J
         return;
     }
     // one inner sweep per round: the outer tournament then acts as one cyclic ordering
-    const bool any =
-        jacobi_orth_t<0>(sm, nloc, len, len, s_nrm, &s_flag, zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
+    const bool any = jacobi_orth_t<E, 16>(sm, nloc, E > 0 ? ld : len, ld, s_nrm, &s_flag,
+                                          zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
     if (!any) return;
-    for (size_t e = tid; e < (size_t)nloc * len; e += JT) {
-        const int j = (int)(e / len), l = (int)(e % len);
+    for (size_t e = tid; e < (size_t)nloc * ld; e += NT) {
+        const int j = (int)(e / ld), l = (int)(e % ld);
+        if (l >= len) continue;
         const int gj = j < cnt[0] ? idx[0] + j : idx[1] + (j - cnt[0]);
         d.X[(size_t)gj * len + l] = sm[e];
     }
@@ -700,7 +708,9 @@ hipError_t jacobi_init(int device) {
     const void* kernels[] = {(const void*)jacobi_lds_kernel<0>, (const void*)jacobi_lds_kernel<1>,
                              (const void*)jacobi_lds_kernel<2>, (const void*)jacobi_lds_kernel<4>,
                              (const void*)jacobi_lds_kernel<8>, (const void*)jacobi_lds_kernel<16>,
-                             (const void*)jacobi_panel_kernel};
+                             (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
+                             (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
+                             (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -732,8 +742,17 @@ bool jacobi_fits_lds(int nvec_cap, int len_cap) {
 int jacobi_lds_class(int len_cap) { return elems_for(len_cap); }
 size_t jacobi_lds_bytes(int nvec_cap, int len_cap) { return lds_need(nvec_cap, len_cap); }
 
+// Rows per block of the batched blocked path and the LDS its workgroups need:
+// two blocks of rows of length 16 E (zero padded, register path) or len_cap.
+static size_t panel_ld(int len_cap) {
+    const int e = elems_for(len_cap);
+    return e > 0 ? 16 * (size_t)e : (size_t)len_cap;
+}
+
+size_t jacobi_panel_bytes(int len_cap, int bs) { return sizeof(double) * 2 * (size_t)bs * panel_ld(len_cap); }
+
 void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) {
-    int bs = (int)((g_lds_bytes - 4096) / (2 * sizeof(double) * (size_t)len_cap));
+    int bs = (int)((g_lds_bytes - 4096) / (2 * sizeof(double) * panel_ld(len_cap)));
     if (bs > 32) bs = 32;
     if (bs < 1) bs = 1;
     int nblk = (nvec_cap + bs - 1) / bs;
@@ -901,9 +920,19 @@ hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max
     JacobiDesc none{};
     hipLaunchKernelGGL(jacobi_reset_kernel, dim3(1), dim3(256), 0, s, arr, count);
     hipLaunchKernelGGL(fro2_kernel, dim3(count), dim3(JT), 0, s, none, arr);
+    const int E = elems_for(len_cap);
+    const dim3 grid(max_pairs, count), block(lds_threads(E));
     for (int sw = 0; sw < sweeps; ++sw) {
-        for (int rd = 0; rd < max_nblk - 1; ++rd)
-            hipLaunchKernelGGL(jacobi_panel_kernel, dim3(max_pairs, count), dim3(JT), shm, s, none, arr, rd);
+        for (int rd = 0; rd < max_nblk - 1; ++rd) {
+            switch (E) {
+                case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, grid, block, shm, s, none, arr, rd); break;
+                case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, grid, block, shm, s, none, arr, rd); break;
+                case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, grid, block, shm, s, none, arr, rd); break;
+                case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, grid, block, shm, s, none, arr, rd); break;
+                case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, grid, block, shm, s, none, arr, rd); break;
+                default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, grid, block, shm, s, none, arr, rd); break;
+            }
+        }
         hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(1), dim3(256), 0, s, arr, count);
     }
     hipLaunchKernelGGL(jacobi_check_done_kernel, dim3(1), dim3(256), 0, s, arr, count);

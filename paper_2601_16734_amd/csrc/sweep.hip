@@ -1026,7 +1026,7 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                         pl.max_nblk = std::max(pl.max_nblk, d.nblk);
                         pl.max_rows = std::max(pl.max_rows, d.basis ? std::max(o->cap0, o->cap1) : o->cap0);
                         pl.cap1 = std::max(pl.cap1, o->cap1);
-                        pl.shm = std::max(pl.shm, sizeof(double) * 2 * (size_t)d.bs * o->cap1);
+                        pl.shm = std::max(pl.shm, jacobi_panel_bytes(o->cap1, d.bs));
                     }
                 }
                 for (auto& cls : lds) {

@@ -158,6 +158,13 @@ def test_invalid_arguments_rejected(ctx):
     with pytest.raises(B.SmpsError) as e:
         ctx.mpo_apply(U3, v, B.strategy(4, 1e-10))
     assert e.value.code == B.EINVAL
+    # a destroyed handle is rejected, not dereferenced
+    v.destroy()
+    with pytest.raises(B.SmpsError) as e:
+        ctx.mpo_apply(U, v, B.strategy(4, 1e-10))
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.SmpsError):
+        v.shape()
 
 
 def test_nonfinite_input_reports_numeric_error(ctx):
