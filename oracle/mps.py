@@ -318,6 +318,69 @@ def apply_simplify_explicit(mpo, mps, max_bond: int, tol: float, sweeps: int = 4
     return res
 
 
+def combine(terms, max_bond: int, tol: float, sweeps: int = 4, mode: int = REL_NORM2) -> SweepResult:
+    """Compression of a linear combination (Sec. 2.4.1, Eq. mps-sum-opt):
+    psi ~ sum_l w_l U_l v_l, terms = [(w_l, mpo_l or None, mps_l)], by the
+    two-site sweep of route F with one set of three-layer environments per
+    term; the local minimiser is the sum of the terms' projections,
+    theta = sum_l w_l theta_l.  The guess is the first term's state."""
+    L = len(terms[0][2])
+    T = []
+    for w, mpo, mps in terms:
+        A = [np.asarray(x, dtype=np.float64) for x in mps]
+        if mpo is None:
+            B = [np.eye(a.shape[1]).reshape(1, a.shape[1], a.shape[1], 1) for a in A]
+        else:
+            B = [np.asarray(x, dtype=np.float64) for x in mpo]
+        T.append((float(w), B, A))
+    psi = right_canonical(T[0][2])
+    one = np.ones((1, 1, 1))
+    Lenv = [[None] * (L + 1) for _ in T]
+    Renv = [[None] * (L + 1) for _ in T]
+    for i in range(len(T)):
+        Lenv[i][0] = one
+        Renv[i][L] = one
+
+    def grow_left(E, P, Bk, Ak):
+        return chain("abx,asc,bspd,xpy->cdy", E, P, Bk, Ak)
+
+    def grow_right(E, P, Bk, Ak):
+        return chain("cdy,asc,bspd,xpy->abx", E, P, Bk, Ak)
+
+    for i, (_, B, A) in enumerate(T):
+        for k in range(L - 1, 0, -1):
+            Renv[i][k] = grow_right(Renv[i][k + 1], psi[k], B[k], A[k])
+    res = SweepResult(mps=psi, norm=0.0, ranks=[])
+    if L == 1:
+        psi[0] = sum(w * np.einsum("bspd,xpy->bxsdy", B[0], A[0]).reshape(1, B[0].shape[1], 1)
+                     for w, B, A in T)
+        res.norm = norm_from_center(psi, 0)
+        res.ranks = [1, 1]
+        return res
+    for sw in range(sweeps):
+        for direction, bonds in ((+1, range(0, L - 1)), (-1, range(L - 2, -1, -1))):
+            for k in bonds:
+                th = sum(w * chain("abx,xpy,bspe,yqz,etqf,cfz->astc", Lenv[i][k], A[k], B[k], A[k + 1],
+                                   B[k + 1], Renv[i][k + 2])
+                         for i, (w, B, A) in enumerate(T))
+                a, s, t, c = th.shape
+                left, right, r, delta, S = _split(th, a, s, t, c, tol, max_bond, mode, direction)
+                psi[k], psi[k + 1] = left, right
+                res.deltas.append(delta)
+                res.norms2.append(float(np.sum(S[:r] ** 2)))
+                res.step_ranks.append(r)
+                for i, (_, B, A) in enumerate(T):
+                    if direction > 0:
+                        Lenv[i][k + 1] = grow_left(Lenv[i][k], psi[k], B[k], A[k])
+                    else:
+                        Renv[i][k + 1] = grow_right(Renv[i][k + 2], psi[k + 1], B[k + 1], A[k + 1])
+    res.mps = psi
+    res.norm = norm_from_center(psi, 0)
+    res.ranks = [1] + [p.shape[2] for p in psi]
+    res.error_bound = float(np.sum(np.sqrt(res.deltas)))
+    return res
+
+
 def simplify(mps, max_bond: int, tol: float, sweeps: int = 4, mode: int = REL_NORM2) -> SweepResult:
     """Compression of a single MPS (Eq. simplification with phi = v): the same
     sweep with the identity operator (bond 1)."""

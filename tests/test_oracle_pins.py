@@ -442,3 +442,46 @@ def test_sketched_sweep_matches_exact_sweep_when_sketches_are_accepted():
         assert abs(got.norm - exact.norm) < 1e-12 * exact.norm
         f = om.scprod(got.mps, exact.mps) / (got.norm * exact.norm)
         assert abs(1 - f) < 1e-12
+
+
+# ---- linear combinations (Sec. 2.4.1, Eq. mps-sum-opt) --------------------------
+
+def _small_terms(seed, L=6, chi=3, D=2, n=3):
+    rng = np.random.default_rng(seed)
+    terms = []
+    for i in range(n):
+        mps = synth.random_mps(rng, L, 2, chi)
+        mpo = None if i == 1 else synth.random_mpo(rng, L, 2, D)
+        terms.append((float(rng.uniform(-2, 2)), mpo, mps))
+    return terms
+
+
+def test_combination_without_truncation_is_the_dense_sum():
+    terms = _small_terms(40)
+    res = om.combine(terms, max_bond=64, tol=0.0, sweeps=2)
+    want = sum(w * (dense.mpo_to_dense(m) @ dense.mps_to_dense(v) if m is not None else dense.mps_to_dense(v))
+               for w, m, v in terms)
+    got = dense.mps_to_dense(res.mps)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_combination_of_one_term_is_the_apply():
+    rng = np.random.default_rng(41)
+    mps = synth.random_mps(rng, 8, 2, 6)
+    mpo = synth.random_mpo(rng, 8, 2, 3)
+    a = om.combine([(1.0, mpo, mps)], max_bond=5, tol=1e-10, sweeps=2)
+    b = om.apply_simplify(mpo, mps, 5, 1e-10, sweeps=2)
+    assert a.ranks == b.ranks
+    assert abs(a.norm - b.norm) <= 1e-12 * b.norm
+    np.testing.assert_allclose(a.deltas, b.deltas, rtol=1e-9, atol=1e-15)
+
+
+def test_combination_is_linear_in_the_weights():
+    rng = np.random.default_rng(42)
+    mps = synth.random_mps(rng, 7, 2, 5)
+    mpo = synth.random_mpo(rng, 7, 2, 2)
+    a = om.combine([(0.3, mpo, mps), (1.2, mpo, mps)], max_bond=4, tol=1e-10, sweeps=2)
+    b = om.combine([(1.5, mpo, mps)], max_bond=4, tol=1e-10, sweeps=2)
+    assert a.ranks == b.ranks
+    f = om.scprod(a.mps, b.mps) / (a.norm * b.norm)
+    assert abs(1 - f) <= 1e-12 and abs(a.norm - b.norm) <= 1e-12 * b.norm
