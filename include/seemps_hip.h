@@ -179,6 +179,20 @@ int smps_last_log(const smps_ctx *ctx, int max_steps, double *deltas, int *ranks
    receives the number of steps available. */
 int smps_last_factor_log(const smps_ctx *ctx, int max_steps, int *kinds, int *steps);
 
+/* Compression of a linear combination (Sec. 2.4.1, Eq. mps-sum-opt):
+   *out ~ sum_l w[l] U[l] v[l], the minimiser over MPS of bond <= max_bond of
+   || psi - sum_l w[l] U[l] v[l] ||^2 by the same two-site sweep as mpo_apply,
+   with one set of three-layer environments per term (the local minimiser is
+   the weighted sum of the terms' projections).  n >= 1 terms; w: n finite
+   host doubles; U: n operator handles, or NULL, or NULL entries (identity);
+   v: n state handles sharing L and the physical dimensions (operators must be
+   square, as in mpo_apply).  The guess is v[0] (its bonds are the starting
+   bonds).  Single-problem path; the result is canonical at site 0 and owned
+   by the caller.  Errors: SMPS_EINVAL for bad arguments, otherwise as
+   smps_mpo_apply. */
+int smps_combine(smps_ctx *ctx, int n, const double *w, const smps_mpo *const *U, const smps_mps *const *v,
+                 const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+
 /* Batched apply: n independent (U[i], v[i]) problems of arbitrary length and
    bonds under one strategy, advanced together bond step by bond step; the
    launch sequence is captured once in a HIP graph per batch shape and replayed.

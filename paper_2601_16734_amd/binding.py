@@ -30,7 +30,7 @@ EXPORTS = [
     "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
-    "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
@@ -88,6 +88,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_last_info": (c_int, [vp, POINTER(ApplyInfo)]),
         "smps_last_log": (c_int, [vp, c_int, dp, ip, dp, ip]),
         "smps_last_factor_log": (c_int, [vp, c_int, ip, ip]),
+        "smps_combine": (c_int, [vp, c_int, dp, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
         "smps_mpo_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
         "smps_scprod": (c_int, [vp, vp, vp, dp]),
         "smps_norm": (c_int, [vp, vp, dp]),
@@ -266,6 +267,17 @@ class Context:
         out = c_void_p()
         err = c_double()
         self._check(self.lib.smps_simplify(self.h, v.h, byref(st), byref(out), byref(err)))
+        return MPS(self, out), err.value
+
+    def combine(self, terms, st: Strategy):
+        """Compress sum_l w_l U_l v_l; terms = [(w, MPO or None, MPS)]."""
+        n = len(terms)
+        w = (c_double * n)(*[float(t[0]) for t in terms])
+        U = (c_void_p * n)(*[t[1].h if t[1] is not None else None for t in terms])
+        v = (c_void_p * n)(*[t[2].h for t in terms])
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_combine(self.h, n, w, U, v, byref(st), byref(out), byref(err)))
         return MPS(self, out), err.value
 
     def mpo_apply_batched(self, Us, vs, st: Strategy):

@@ -400,6 +400,58 @@ int smps_simplify(smps_ctx* c, const smps_mps* v, const smps_strategy* st, smps_
     return rc;
 }
 
+// identity operator with bond 1 on the site spaces of v
+static int identity_mpo(smps_ctx* c, const smps_mps* v, smps_mpo** I) {
+    std::vector<int> bonds(v->L + 1, 1);
+    std::vector<std::vector<double>> eye(v->L);
+    std::vector<const void*> ptrs(v->L);
+    for (int k = 0; k < v->L; ++k) {
+        const int d = v->phys[k];
+        eye[k].assign((size_t)d * d, 0.0);
+        for (int i = 0; i < d; ++i) eye[k][(size_t)i * d + i] = 1.0;
+        ptrs[k] = eye[k].data();
+    }
+    return smps_mpo_create(c, v->L, v->phys.data(), v->phys.data(), bonds.data(), SMPS_F64, ptrs.data(), I);
+}
+
+// Compression of a linear combination (Sec. 2.4.1, Eq. mps-sum-opt).
+int smps_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
+                 const smps_strategy* st, smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !w || !v) return fail(c, SMPS_EINVAL, "a combination needs n >= 1 weights and states");
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (!v[i]) return fail(c, SMPS_EINVAL, "NULL state handle");
+        if (!std::isfinite(w[i])) return fail(c, SMPS_EINVAL, "weights must be finite");
+        if (v[i]->L != v[0]->L || v[i]->phys != v[0]->phys)
+            return fail(c, SMPS_EINVAL, "the states of a combination must share length and physical dimensions");
+        if (U && U[i]) {
+            rc = check_pair(c, U[i], v[i]);
+            if (rc) return rc;
+        }
+    }
+    SMPS_HIP(c, hipSetDevice(c->device));
+    std::vector<const smps_mpo*> ops(n);
+    std::vector<smps_mpo*> owned;
+    for (int i = 0; i < n; ++i) {
+        if (U && U[i]) {
+            ops[i] = U[i];
+            continue;
+        }
+        smps_mpo* I = nullptr;
+        rc = identity_mpo(c, v[i], &I);
+        if (rc) break;
+        owned.push_back(I);
+        ops[i] = I;
+    }
+    if (rc == SMPS_OK) rc = run_combine(c, n, w, ops.data(), v, *st, out, trunc_err);
+    for (smps_mpo* I : owned) smps_mpo_destroy(I);
+    return rc;
+}
+
 int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                            const smps_strategy* st, smps_mps** out, double* trunc_err) {
     if (!c) return SMPS_EINVAL;

@@ -41,6 +41,7 @@ struct GemmDesc {
     int ta, tb, tc;
     int a_type, b_type, c_type;  // DType
     double alpha;
+    double beta;  // C = alpha op(A) op(B) + beta C (beta = 0: C is not read)
     // batching: pointer strides in elements per blockIdx.z (0 for unbatched)
     long long sA, sB, sC;
 };
@@ -170,6 +171,9 @@ hipError_t launch_sumsq(const double* x, const int* dims, DimExpr n, int n_cap, 
 hipError_t launch_check_finite(const double* x, const int* dims, DimExpr n, int n_cap, int* status,
                                hipStream_t s);
 hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipStream_t s);
+// y = a x + b y over m * n doubles (m, n from dims)
+hipError_t launch_axpby(double* y, const double* x, double a, double b, const int* dims, DimExpr m, DimExpr n,
+                        int cap, hipStream_t s);
 // randomized factorization pieces (rsvd.hip)
 hipError_t launch_sketch(double* G, int rows, int nvec, unsigned long long step, hipStream_t s);
 hipError_t launch_rank_features(const double* lspec, int first, int stride, int count, float* feats, hipStream_t s);

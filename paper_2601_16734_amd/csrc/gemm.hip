@@ -118,6 +118,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         __syncthreads();
     }
     const CT alpha = (CT)g.alpha;
+    const double beta = g.beta;
     for (int i = 0; i < FM; ++i)
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) {
@@ -126,7 +127,10 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
                 const int col = n0 + wn + j * 16 + li;
                 if (row < M && col < N) {
                     const size_t o = g.tc ? (size_t)col * M + row : (size_t)row * N + col;
-                    ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
+                    if (beta != 0.0)
+                        ((TC*)C)[o] = (TC)((double)(alpha * acc[i][j][v]) + beta * (double)((TC*)C)[o]);
+                    else
+                        ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
                 }
             }
 }
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         __syncthreads();
     }
     const float alpha = (float)g.alpha;
+    const double beta = g.beta;
     for (int i = 0; i < FM; ++i)
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) {
@@ -216,7 +221,10 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
                 const int col = n0 + wn + j * 16 + li;
                 if (row < M && col < N) {
                     const size_t o = g.tc ? (size_t)col * M + row : (size_t)row * N + col;
-                    ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
+                    if (beta != 0.0)
+                        ((TC*)C)[o] = (TC)((double)(alpha * acc[i][j][v]) + beta * (double)((TC*)C)[o]);
+                    else
+                        ((TC*)C)[o] = (TC)(alpha * acc[i][j][v]);
                 }
             }
 }

@@ -71,6 +71,20 @@ struct Plan {
     int steps = 0;
     size_t max_theta = 0, max_tmp = 0, max_env = 0, max_xr = 0;
     int max_nvec = 0;
+    // linear combinations: the first term lives in the fields above (its state
+    // is the guess); every further term has its own operator, state, weight and
+    // environment buffers
+    double w0 = 1.0;
+    struct Term {
+        const smps_mpo* U;
+        const smps_mps* v;
+        double w;
+        std::vector<int> dv, Dm, chiv;
+        std::vector<size_t> o_L, o_R, o_XL, o_XR;
+        size_t o_tmp = 0;
+    };
+    std::vector<Term> more;
+    size_t o_cacc = 0;  // centre accumulation scratch (mixed precision, several terms)
 };
 
 void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, Layout& lay) {
@@ -187,6 +201,58 @@ void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_stra
 }
 
 
+// Buffers of the further terms of a linear combination; the mixed-precision
+// FP64 scratch of the first term is grown to the largest term.
+void plan_terms(Plan& p, const std::vector<const smps_mpo*>& U, const std::vector<const smps_mps*>& v,
+                const std::vector<double>& w, Layout& lay) {
+    const int L = p.L;
+    const auto& c = p.capb;
+    p.w0 = w[0];
+    size_t max_env = p.max_env, max_xr = p.max_xr, ymax = 0;
+    for (size_t t = 1; t < U.size(); ++t) {
+        Plan::Term T;
+        T.U = U[t];
+        T.v = v[t];
+        T.w = w[t];
+        T.dv = v[t]->phys;
+        T.chiv = v[t]->bonds;
+        T.Dm = U[t]->bonds;
+        T.o_L.resize(L + 1);
+        T.o_R.resize(L + 1);
+        T.o_XL.resize(L);
+        T.o_XR.resize(L);
+        size_t max_tmp = 0;
+        for (int k = 0; k <= L; ++k) {
+            const size_t n = (size_t)c[k] * T.Dm[k] * T.chiv[k];
+            max_env = std::max(max_env, n);
+            T.o_L[k] = lay.add(p.es * n);
+            T.o_R[k] = lay.add(p.es * n);
+        }
+        for (int k = 0; k < L; ++k) {
+            const size_t nxl = (size_t)c[k] * p.e[k] * T.Dm[k + 1] * T.chiv[k + 1];
+            const size_t nxr = (size_t)T.Dm[k] * T.chiv[k] * p.e[k] * c[k + 1];
+            T.o_XL[k] = lay.add(p.es * nxl);
+            T.o_XR[k] = lay.add(p.es * nxr);
+            max_xr = std::max(max_xr, nxr);
+            max_tmp = std::max(max_tmp, (size_t)c[k] * T.Dm[k] * T.dv[k] * T.chiv[k + 1]);
+            max_tmp = std::max(max_tmp, (size_t)T.chiv[k] * T.dv[k] * c[k + 1] * T.Dm[k + 1]);
+            ymax = std::max(ymax, (size_t)T.chiv[k] * T.dv[k] * c[k + 1] * T.Dm[k + 1]);
+        }
+        T.o_tmp = lay.add(p.es * max_tmp);
+        p.more.push_back(std::move(T));
+    }
+    if (p.et != T_F64 && !p.more.empty()) {
+        // FP64 rebuild scratch large enough for every term, and a centre accumulator
+        for (int k = 0; k < L; ++k)
+            ymax = std::max(ymax, (size_t)p.chiv[k] * p.dv[k] * c[k + 1] * p.Dm[k + 1]);
+        p.o_R64a = lay.add(8 * max_env);
+        p.o_R64b = lay.add(8 * max_env);
+        p.o_XR64 = lay.add(8 * max_xr);
+        p.o_Y64 = lay.add(8 * ymax);
+        p.o_cacc = lay.add(8 * max_xr);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Operations.  The sequence of one problem is produced by Enq::run(); every
 // operation carries an alignment tag (major phase, step j inside the phase,
@@ -237,8 +303,21 @@ struct Enq {
 
     template <typename T = void>
     T* at(size_t off) const { return (T*)(base + off); }
-    const double* vsite(int k) const { return v->data + v->off[k]; }
-    const double* usite(int k) const { return U->data + U->off[k]; }
+    // term t of a linear combination (t = 0: the fields of the plan itself)
+    int nterms() const { return 1 + (int)p.more.size(); }
+    const smps_mpo* Ut(int t) const { return t ? p.more[t - 1].U : U; }
+    const smps_mps* vt(int t) const { return t ? p.more[t - 1].v : v; }
+    double wt(int t) const { return t ? p.more[t - 1].w : p.w0; }
+    const std::vector<int>& Dm_(int t) const { return t ? p.more[t - 1].Dm : p.Dm; }
+    const std::vector<int>& chiv_(int t) const { return t ? p.more[t - 1].chiv : p.chiv; }
+    const std::vector<int>& dv_(int t) const { return t ? p.more[t - 1].dv : p.dv; }
+    size_t oL(int t, int k) const { return t ? p.more[t - 1].o_L[k] : p.o_L[k]; }
+    size_t oR(int t, int k) const { return t ? p.more[t - 1].o_R[k] : p.o_R[k]; }
+    size_t oXL(int t, int k) const { return t ? p.more[t - 1].o_XL[k] : p.o_XL[k]; }
+    size_t oXR(int t, int k) const { return t ? p.more[t - 1].o_XR[k] : p.o_XR[k]; }
+    size_t otmp(int t) const { return t ? p.more[t - 1].o_tmp : p.o_tmp; }
+    const double* vsite(int k, int t = 0) const { return vt(t)->data + vt(t)->off[k]; }
+    const double* usite(int k, int t = 0) const { return Ut(t)->data + Ut(t)->off[k]; }
     double* centre() const { return p.et == T_F64 ? at<double>(p.o_XR[0]) : at<double>(p.o_XR64); }
 
     void tag(int major, int j) const {
@@ -279,7 +358,8 @@ struct Enq {
     }
 
     hipError_t gemm(const void* A, int ta_type, const void* B, int tb_type, void* C, int tc_type, DimExpr M,
-                    DimExpr N, DimExpr K, int ta, int tb, int tc, int Mcap, int Ncap, int prec) const {
+                    DimExpr N, DimExpr K, int ta, int tb, int tc, int Mcap, int Ncap, int prec, double alpha = 1.0,
+                    double beta = 0.0) const {
         Op op;
         op.kind = OP_GEMM;
         GemmDesc& g = op.g;
@@ -296,11 +376,19 @@ struct Enq {
         g.a_type = ta_type;
         g.b_type = tb_type;
         g.c_type = tc_type;
-        g.alpha = 1.0;
+        g.alpha = alpha;
+        g.beta = beta;
         op.cap0 = Mcap;
         op.cap1 = Ncap;
         op.prec = prec;
         return emit(std::move(op));
+    }
+
+    // y = a x + b y over m * n doubles: only linear combinations use it, and
+    // they run on the single-problem path (no recording)
+    hipError_t axpby(double* y, const double* x, double a, double b, DimExpr m, DimExpr n, int cap) const {
+        if (rec) return hipErrorNotSupported;
+        return launch_axpby(y, x, a, b, dims, m, n, cap, s);
     }
 
     hipError_t copy(const double* src, double* dst, DimExpr a, DimExpr b, int cap) const {
@@ -311,63 +399,70 @@ struct Enq {
         return emit(std::move(op));
     }
 
-    // XL[k] = (Lenv[k] A_k) B_k
-    hipError_t build_XL(int k) const {
+    // XL[k] = (Lenv[k] A_k) B_k of term t
+    hipError_t build_XL(int k, int t = 0) const {
         const auto& c = p.capb;
-        hipError_t e = gemm(at(p.o_L[k]), p.et, vsite(k), T_F64, at(p.o_tmp), p.et, ddyn(k, p.Dm[k]),
-                            dconst(p.dv[k] * p.chiv[k + 1]), dconst(p.chiv[k]), 0, 0, 0, c[k] * p.Dm[k],
-                            p.dv[k] * p.chiv[k + 1], p.prec);
+        const auto& Dm = Dm_(t);
+        const auto& cv = chiv_(t);
+        const auto& dv = dv_(t);
+        hipError_t e = gemm(at(oL(t, k)), p.et, vsite(k, t), T_F64, at(otmp(t)), p.et, ddyn(k, Dm[k]),
+                            dconst(dv[k] * cv[k + 1]), dconst(cv[k]), 0, 0, 0, c[k] * Dm[k], dv[k] * cv[k + 1],
+                            p.prec);
         if (e != hipSuccess) return e;
         Op op;
         op.kind = OP_LEFT;
         LeftMpoDesc& d = op.l;
-        d.X = at(p.o_tmp);
-        d.Y = at(p.o_XL[k]);
-        d.B = usite(k);
+        d.X = at(otmp(t));
+        d.Y = at(oXL(t, k));
+        d.B = usite(k, t);
         d.dims = dims;
         d.a = ddyn(k);
-        d.Dl = p.Dm[k];
+        d.Dl = Dm[k];
         d.e = p.e[k];
-        d.d = p.dv[k];
-        d.Dr = p.Dm[k + 1];
-        d.ny = p.chiv[k + 1];
+        d.d = dv[k];
+        d.Dr = Dm[k + 1];
+        d.ny = cv[k + 1];
         d.x_type = p.et;
         d.y_type = p.et;
         op.cap0 = c[k];
         return emit(std::move(op));
     }
 
-    // XR[k] = B_k (A_k Renv[k+1]^T), with Renv given explicitly (type rt)
-    hipError_t build_XR(int k, const void* Renv, void* tmp, void* XR, int rt, int prec) const {
+    // XR[k] = B_k (A_k Renv[k+1]^T) of term t, with Renv given explicitly (type rt)
+    hipError_t build_XR(int k, const void* Renv, void* tmp, void* XR, int rt, int prec, int t = 0) const {
         const auto& c = p.capb;
-        hipError_t e = gemm(vsite(k), T_F64, Renv, rt, tmp, rt, dconst(p.chiv[k] * p.dv[k]),
-                            ddyn(k + 1, p.Dm[k + 1]), dconst(p.chiv[k + 1]), 0, 1, 0, p.chiv[k] * p.dv[k],
-                            c[k + 1] * p.Dm[k + 1], prec);
+        const auto& Dm = Dm_(t);
+        const auto& cv = chiv_(t);
+        const auto& dv = dv_(t);
+        hipError_t e = gemm(vsite(k, t), T_F64, Renv, rt, tmp, rt, dconst(cv[k] * dv[k]), ddyn(k + 1, Dm[k + 1]),
+                            dconst(cv[k + 1]), 0, 1, 0, cv[k] * dv[k], c[k + 1] * Dm[k + 1], prec);
         if (e != hipSuccess) return e;
         Op op;
         op.kind = OP_RIGHT;
         RightMpoDesc& d = op.r;
         d.X = tmp;
         d.Y = XR;
-        d.B = usite(k);
+        d.B = usite(k, t);
         d.dims = dims;
         d.c = ddyn(k + 1);
-        d.Dl = p.Dm[k];
+        d.Dl = Dm[k];
         d.e = p.e[k];
-        d.d = p.dv[k];
-        d.Dr = p.Dm[k + 1];
-        d.nx = p.chiv[k];
+        d.d = dv[k];
+        d.Dr = Dm[k + 1];
+        d.nx = cv[k];
         d.x_type = rt;
         d.y_type = rt;
         op.cap0 = c[k + 1];
         return emit(std::move(op));
     }
 
-    // Renv[k] = psi_k XR[k]^T
-    hipError_t env_R(int k, const void* XR, void* R, int rt, int prec) const {
+    // Renv[k] = psi_k XR[k]^T of term t
+    hipError_t env_R(int k, const void* XR, void* R, int rt, int prec, int t = 0) const {
         const auto& c = p.capb;
-        return gemm(at(p.o_psi[k]), T_F64, XR, rt, R, rt, ddyn(k), dconst(p.Dm[k] * p.chiv[k]),
-                    ddyn(k + 1, p.e[k]), 0, 1, 0, c[k], p.Dm[k] * p.chiv[k], prec);
+        const auto& Dm = Dm_(t);
+        const auto& cv = chiv_(t);
+        return gemm(at(p.o_psi[k]), T_F64, XR, rt, R, rt, ddyn(k), dconst(Dm[k] * cv[k]), ddyn(k + 1, p.e[k]), 0,
+                    1, 0, c[k], Dm[k] * cv[k], prec);
     }
 
     JacobiDesc jac(double* X, double* Q, DimExpr nvec, DimExpr len, int rank_idx, int max_rank, double tol,
@@ -598,16 +693,17 @@ struct Enq {
             op.set_vals.assign(1, 0);
             CK(emit(std::move(op)));
         }
-        {
+        const int NT = nterms();
+        for (int t = 0; t < NT; ++t) {
             Op a;
             a.kind = OP_FILL;
-            a.fill_dst = at(p.o_L[0]);
+            a.fill_dst = at(oL(t, 0));
             a.fill_type = p.et;
             a.fill_val = 1.0;
             CK(emit(std::move(a)));
             Op b;
             b.kind = OP_FILL;
-            b.fill_dst = at(p.o_R[L]);
+            b.fill_dst = at(oR(t, L));
             b.fill_type = p.et;
             b.fill_val = 1.0;
             CK(emit(std::move(b)));
@@ -644,8 +740,10 @@ struct Enq {
         // ---- right environments of the guess
         for (int k = L - 1; k >= 1; --k) {
             tag(2, L - 1 - k);
-            CK(build_XR(k, at(p.o_R[k + 1]), at(p.o_tmp), at(p.o_XR[k]), p.et, p.prec));
-            CK(env_R(k, at(p.o_XR[k]), at(p.o_R[k]), p.et, p.prec));
+            for (int t = 0; t < NT; ++t) {
+                CK(build_XR(k, at(oR(t, k + 1)), at(otmp(t)), at(oXR(t, k)), p.et, p.prec, t));
+                CK(env_R(k, at(oXR(t, k)), at(oR(t, k)), p.et, p.prec, t));
+            }
         }
         // ---- sweeps (Sec. 2.5)
         int step = 0;
@@ -659,36 +757,46 @@ struct Enq {
             if (rs_lr && !rec) CK(predict_ranks((2 * sw - 1) * (L - 1) + (L - 2), -1));
             for (int k = 0; k + 1 < L; ++k) {  // left to right
                 tag(3 + 2 * sw, k);
-                CK(build_XL(k));
                 double* theta = at<double>(p.o_theta);
-                CK(gemm(at(p.o_XL[k]), p.et, at(p.o_XR[k + 1]), p.et, theta, T_F64, ddyn(k, e[k]),
-                        ddyn(k + 2, e[k + 1]), dconst(p.Dm[k + 1] * p.chiv[k + 1]), 0, 0, 1, c[k] * e[k],
-                        e[k + 1] * c[k + 2], p.prec));
+                // theta = sum_t w_t XL_t[k] XR_t[k+1] (one term: the plain product)
+                for (int t = 0; t < NT; ++t) {
+                    CK(build_XL(k, t));
+                    const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
+                    CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
+                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, 1, c[k] * e[k], e[k + 1] * c[k + 2], p.prec,
+                            wt(t), t ? 1.0 : 0.0));
+                }
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start (sw > 0): rotate by the right singular basis this bond
                 // produced in the previous right-to-left pass (identity when it was not full)
                 CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
                           c[k] * e[k], at<double>(p.o_Q), mr));
-                // Lenv[k+1] = Q XL[k]
-                CK(gemm(at(p.o_Q), T_F64, at(p.o_XL[k]), p.et, at(p.o_L[k + 1]), p.et, ddyn(k + 1),
-                        dconst(p.Dm[k + 1] * p.chiv[k + 1]), ddyn(k, e[k]), 0, 0, 0, c[k + 1],
-                        p.Dm[k + 1] * p.chiv[k + 1], p.prec));
+                // Lenv_t[k+1] = Q XL_t[k]
+                for (int t = 0; t < NT; ++t) {
+                    const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
+                    CK(gemm(at(p.o_Q), T_F64, at(oXL(t, k)), p.et, at(oL(t, k + 1)), p.et, ddyn(k + 1), dconst(K),
+                            ddyn(k, e[k]), 0, 0, 0, c[k + 1], K, p.prec));
+                }
                 ++step;
             }
             // bond k was last factorized in this sweep's left-to-right pass, at step 2 sw (L - 1) + k
             if (rs && !rec) CK(predict_ranks(2 * sw * (L - 1), 1));
             for (int k = L - 2; k >= 0; --k) {  // right to left
                 tag(4 + 2 * sw, L - 2 - k);
-                CK(build_XR(k + 1, at(p.o_R[k + 2]), at(p.o_tmp), at(p.o_XR[k + 1]), p.et, p.prec));
                 double* theta = at<double>(p.o_theta);
-                CK(gemm(at(p.o_XL[k]), p.et, at(p.o_XR[k + 1]), p.et, theta, T_F64, ddyn(k, e[k]),
-                        ddyn(k + 2, e[k + 1]), dconst(p.Dm[k + 1] * p.chiv[k + 1]), 0, 0, 0, c[k] * e[k],
-                        e[k + 1] * c[k + 2], p.prec));
+                for (int t = 0; t < NT; ++t) {
+                    CK(build_XR(k + 1, at(oR(t, k + 2)), at(otmp(t)), at(oXR(t, k + 1)), p.et, p.prec, t));
+                    const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
+                    CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
+                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, 0, c[k] * e[k], e[k + 1] * c[k + 2], p.prec,
+                            wt(t), t ? 1.0 : 0.0));
+                }
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start from the left singular basis of this pass's left-to-right visit
                 CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
                           e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
-                CK(env_R(k + 1, at(p.o_XR[k + 1]), at(p.o_R[k + 1]), p.et, p.prec));
+                for (int t = 0; t < NT; ++t)
+                    CK(env_R(k + 1, at(oXR(t, k + 1)), at(oR(t, k + 1)), p.et, p.prec, t));
                 ++step;
             }
             sweeps_done = sw + 1;
@@ -706,27 +814,44 @@ struct Enq {
         // ---- centre tensor psi_0 = B_0 A_0 Renv[1]: an exact projection on the
         // final right isometries; in the mixed precisions the right
         // environments are rebuilt in FP64 first.
+        // A linear combination sums the terms' projections: psi_0 = sum_t w_t B_0 A_0 Renv_t[1].
+        const bool weighted = NT > 1 || p.w0 != 1.0;
+        const DimExpr cm = dconst(e[0]), cn = ddyn(1);
         if (p.et == T_F64) {
             tag(4 + 2 * S, 0);
-            CK(build_XR(0, at(p.o_R[1]), at(p.o_tmp), at(p.o_XR[0]), T_F64, P_F64));
-        } else {
-            double* Ra = at<double>(p.o_R64a);
-            double* Rb = at<double>(p.o_R64b);
-            tag(3 + 2 * S, 0);
-            Op f;
-            f.kind = OP_FILL;
-            f.fill_dst = Ra;
-            f.fill_type = T_F64;
-            f.fill_val = 1.0;
-            CK(emit(std::move(f)));
-            for (int k = L - 1; k >= 1; --k) {
-                tag(3 + 2 * S, 1 + (L - 1 - k));
-                CK(build_XR(k, Ra, at(p.o_Y64), at(p.o_XR64), T_F64, P_F64));
-                CK(env_R(k, at(p.o_XR64), Rb, T_F64, P_F64));
-                std::swap(Ra, Rb);
+            for (int t = 0; t < NT; ++t) {
+                CK(build_XR(0, at(oR(t, 1)), at(otmp(t)), at(oXR(t, 0)), T_F64, P_F64, t));
+                if (t == 0 && weighted) CK(axpby(centre(), centre(), 0.0, p.w0, cm, cn, e[0] * c[1]));
+                if (t > 0) CK(axpby(centre(), at<double>(oXR(t, 0)), wt(t), 1.0, cm, cn, e[0] * c[1]));
             }
-            tag(4 + 2 * S, 0);
-            CK(build_XR(0, Ra, at(p.o_Y64), at(p.o_XR64), T_F64, P_F64));
+        } else {
+            for (int t = 0; t < NT; ++t) {
+                double* Ra = at<double>(p.o_R64a);
+                double* Rb = at<double>(p.o_R64b);
+                tag(3 + 2 * S, 0);
+                Op f;
+                f.kind = OP_FILL;
+                f.fill_dst = Ra;
+                f.fill_type = T_F64;
+                f.fill_val = 1.0;
+                CK(emit(std::move(f)));
+                // term 0 leaves its projection in XR64 (the centre); later terms work in cacc
+                void* xr = at(t == 0 ? p.o_XR64 : p.o_cacc);
+                for (int k = L - 1; k >= 1; --k) {
+                    tag(3 + 2 * S, 1 + (L - 1 - k));
+                    CK(build_XR(k, Ra, at(p.o_Y64), xr, T_F64, P_F64, t));
+                    CK(env_R(k, xr, Rb, T_F64, P_F64, t));
+                    std::swap(Ra, Rb);
+                }
+                tag(4 + 2 * S, 0);
+                if (t == 0) {
+                    CK(build_XR(0, Ra, at(p.o_Y64), at(p.o_XR64), T_F64, P_F64, t));
+                    if (weighted) CK(axpby(centre(), centre(), 0.0, p.w0, cm, cn, e[0] * c[1]));
+                } else {
+                    CK(build_XR(0, Ra, at(p.o_Y64), at(p.o_cacc), T_F64, P_F64, t));
+                    CK(axpby(centre(), at<double>(p.o_cacc), wt(t), 1.0, cm, cn, e[0] * c[1]));
+                }
+            }
         }
         tag(5 + 2 * S, 0);
         {
@@ -805,24 +930,40 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
     return SMPS_OK;
 }
 
-int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
-              double* trunc_err) {
+// One chain, one or several (weight, operator, state) terms; the first term's
+// state is the guess.
+static int run_terms(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
+                     const smps_strategy& st, smps_mps** out, double* trunc_err) {
     Plan p;
     Layout lay;
-    plan_problem(p, U, v, st, lay);
+    plan_problem(p, U[0], v[0], st, lay);
     if (p.max_nvec > 2048)
         return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
+    if (n > 1 || w[0] != 1.0)
+        plan_terms(p, std::vector<const smps_mpo*>(U, U + n), std::vector<const smps_mps*>(v, v + n),
+                   std::vector<double>(w, w + n), lay);
     int rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     if (st.factorization == SMPS_FACT_RSVD_MLP && !mlp_ready(c))
         return fail(c, SMPS_EINVAL, "the randomized factorization sized by the rank predictor needs "
                                     "smps_rank_mlp_init, _set or _train first");
-    Enq q{p, U, v, st, c->arena, c->stream, (int*)(c->arena + p.o_dims)};
+    Enq q{p, U[0], v[0], st, c->arena, c->stream, (int*)(c->arena + p.o_dims)};
     q.ctx = c;
     hipError_t e = q.run();
     if (e != hipSuccess)
         return fail(c, SMPS_EHIP, std::string("enqueue failed at ") + q.where + ": " + hipGetErrorString(e));
     return finish(c, p, q, st, out, trunc_err);
+}
+
+int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy& st, smps_mps** out,
+              double* trunc_err) {
+    const double one = 1.0;
+    return run_terms(c, 1, &one, &U, &v, st, out, trunc_err);
+}
+
+int run_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
+                const smps_strategy& st, smps_mps** out, double* trunc_err) {
+    return run_terms(c, n, w, U, v, st, out, trunc_err);
 }
 
 // Autotune every product shape one apply + compression would launch: the

@@ -1,6 +1,7 @@
 // Small device utilities: copies sized by device-resident dimensions, fills,
 // FP64 sum of squares (the Frobenius norm of a centre tensor) and checks.
 
+#include <algorithm>
 #include <cfloat>
 
 #include "common.h"
@@ -195,6 +196,21 @@ __global__ __launch_bounds__(1024) void norm_check_batched_kernel(const NormDesc
 hipError_t launch_norm_check_batched(const NormDesc* arr, int count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(norm_check_batched_kernel, dim3(count), dim3(1024), 0, s, arr);
+    return hipGetLastError();
+}
+
+__global__ void axpby_kernel(double* y, const double* x, double a, double b, const int* dims, DimExpr me,
+                             DimExpr ne) {
+    const long long n = (long long)eval_dim(dims, me) * eval_dim(dims, ne);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        y[i] = a * x[i] + b * y[i];
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, double b, const int* dims, DimExpr m, DimExpr n,
+                        int cap, hipStream_t s) {
+    if (cap <= 0) return hipSuccess;
+    const int blocks = std::min(1024, (cap + 255) / 256);
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks), dim3(256), 0, s, y, x, a, b, dims, m, n);
     return hipGetLastError();
 }
 
