@@ -41,7 +41,7 @@ typedef enum {
     SMPS_ENOMEM = -2,       /* device allocation failed or a workspace limit was exceeded */
     SMPS_EHIP = -3,         /* a HIP runtime call failed */
     SMPS_ENUMERIC = -4,     /* non-finite values met in a factorization */
-    SMPS_EUNSUPPORTED = -5  /* valid request this build does not handle */
+    SMPS_EUNSUPPORTED = -5  /* valid request the library does not handle */
 } smps_status;
 
 /* storage type of host data handed to *_create */

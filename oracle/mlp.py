@@ -1,6 +1,6 @@
 """FP64 reference of the rank-predicting multilayer perceptron (test
 infrastructure only; the paper has no learned component -- this network and
-its loss are this build's own choices, stated in the design notes).
+its loss are choices of this library, not of the paper).
 
 Network: x (32) -> ReLU(W1 x + b1) (64) -> ReLU(W2 h1 + b2) (64) -> W3 h2 + b3 (1).
 The forward pass uses the weights rounded to bfloat16 (round to nearest even),
