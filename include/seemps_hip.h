@@ -141,6 +141,11 @@ int smps_mps_destroy(smps_mps *mps);
 int smps_mps_shape(const smps_mps *mps, int *L, int *phys, int *bonds, int *center);
 /* Copy site tensor `site` (FP64, C order) into host_out; count must equal its size. */
 int smps_mps_read(smps_ctx *ctx, const smps_mps *mps, int site, double *host_out, size_t count);
+/* Shape and site read-back of an operator: pout / pin (L ints each), bonds
+   (L+1 ints), any may be NULL; site k is (bonds[k], pout[k], pin[k],
+   bonds[k+1]) doubles in C order and count must equal that size. */
+int smps_mpo_shape(const smps_mpo *mpo, int *L, int *pout, int *pin, int *bonds);
+int smps_mpo_read(smps_ctx *ctx, const smps_mpo *mpo, int site, double *host_out, size_t count);
 /* Device pointer of site tensor `site` (FP64, C order, owned by the handle). */
 int smps_mps_device_ptr(const smps_mps *mps, int site, const double **ptr);
 
@@ -192,6 +197,25 @@ int smps_last_factor_log(const smps_ctx *ctx, int max_steps, int *kinds, int *st
    smps_mpo_apply. */
 int smps_combine(smps_ctx *ctx, int n, const double *w, const smps_mpo *const *U, const smps_mps *const *v,
                  const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+
+/* Operator utilities (Sec. 2.4.1-2.4.3), built on mpo_apply / simplify:
+ *   smps_mpo_transpose: new operator with the out and in indices of every site
+ *       exchanged (in real arithmetic, the adjoint); caller owns *out.
+ *   smps_mpo_apply_right: v @ U, the operator applied from the right
+ *       (Sec. 2.4.2), computed as mpo_apply(U^T, v); same contract as mpo_apply.
+ *   smps_mpo_list_apply: U[n-1] ... U[1] U[0] v applied one operator at a
+ *       time, compressing after each product (Sec. 2.4.3); *trunc_err
+ *       (nullable) receives the sum of the steps' error bounds.
+ *   smps_mpo_simplify: compression of an operator (simplify_mpo, Sec. 2.4.1):
+ *       the sites read as an MPS of site dimension out*in, compressed by
+ *       simplify under the strategy, and returned as a new operator. */
+int smps_mpo_transpose(smps_ctx *ctx, const smps_mpo *U, smps_mpo **out);
+int smps_mpo_apply_right(smps_ctx *ctx, const smps_mps *v, const smps_mpo *U, const smps_strategy *strategy,
+                         smps_mps **out, double *trunc_err);
+int smps_mpo_list_apply(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *v,
+                        const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+int smps_mpo_simplify(smps_ctx *ctx, const smps_mpo *U, const smps_strategy *strategy, smps_mpo **out,
+                      double *trunc_err);
 
 /* Batched apply: n independent (U[i], v[i]) problems of arbitrary length and
    bonds under one strategy, advanced together bond step by bond step; the

@@ -30,7 +30,8 @@ EXPORTS = [
     "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
-    "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_transpose",
+    "smps_mpo_apply_right", "smps_mpo_list_apply", "smps_mpo_simplify", "smps_mpo_shape", "smps_mpo_read", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
@@ -89,6 +90,12 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_last_log": (c_int, [vp, c_int, dp, ip, dp, ip]),
         "smps_last_factor_log": (c_int, [vp, c_int, ip, ip]),
         "smps_combine": (c_int, [vp, c_int, dp, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
+        "smps_mpo_transpose": (c_int, [vp, vp, POINTER(vp)]),
+        "smps_mpo_shape": (c_int, [vp, ip, ip, ip, ip]),
+        "smps_mpo_read": (c_int, [vp, vp, c_int, dp, c_size_t]),
+        "smps_mpo_apply_right": (c_int, [vp, vp, vp, POINTER(Strategy), POINTER(vp), dp]),
+        "smps_mpo_list_apply": (c_int, [vp, c_int, POINTER(vp), vp, POINTER(Strategy), POINTER(vp), dp]),
+        "smps_mpo_simplify": (c_int, [vp, vp, POINTER(Strategy), POINTER(vp), dp]),
         "smps_mpo_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
         "smps_scprod": (c_int, [vp, vp, vp, dp]),
         "smps_norm": (c_int, [vp, vp, dp]),
@@ -175,10 +182,31 @@ class MPS:
 
 
 class MPO:
+    """Handle of a device MPO (owned; freed on destroy / garbage collection)."""
+
     def __init__(self, ctx: "Context", handle: c_void_p, L: int):
         self.ctx = ctx
         self.h = handle
         self.L = L
+
+    def shape(self):
+        if not self.h:
+            raise SmpsError(EINVAL, "MPO handle was destroyed")
+        pout = (c_int * self.L)()
+        pin = (c_int * self.L)()
+        bonds = (c_int * (self.L + 1))()
+        self.ctx._check(self.ctx.lib.smps_mpo_shape(self.h, None, pout, pin, bonds))
+        return list(pout), list(pin), list(bonds)
+
+    def read(self) -> list[np.ndarray]:
+        pout, pin, bonds = self.shape()
+        out = []
+        for k in range(self.L):
+            a = np.empty((bonds[k], pout[k], pin[k], bonds[k + 1]), dtype=np.float64)
+            self.ctx._check(self.ctx.lib.smps_mpo_read(self.ctx.h, self.h, k, a.ctypes.data_as(POINTER(c_double)),
+                                                      a.size))
+            out.append(a)
+        return out
 
     def destroy(self):
         if self.h:
@@ -279,6 +307,31 @@ class Context:
         err = c_double()
         self._check(self.lib.smps_combine(self.h, n, w, U, v, byref(st), byref(out), byref(err)))
         return MPS(self, out), err.value
+
+    def mpo_transpose(self, U: "MPO") -> "MPO":
+        out = c_void_p()
+        self._check(self.lib.smps_mpo_transpose(self.h, U.h, byref(out)))
+        return MPO(self, out, U.L)
+
+    def mpo_apply_right(self, v: "MPS", U: "MPO", st: Strategy):
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_mpo_apply_right(self.h, v.h, U.h, byref(st), byref(out), byref(err)))
+        return MPS(self, out), err.value
+
+    def mpo_list_apply(self, Us, v: "MPS", st: Strategy):
+        n = len(Us)
+        uh = (c_void_p * n)(*[u.h for u in Us])
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_mpo_list_apply(self.h, n, uh, v.h, byref(st), byref(out), byref(err)))
+        return MPS(self, out), err.value
+
+    def mpo_simplify(self, U: "MPO", st: Strategy):
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_mpo_simplify(self.h, U.h, byref(st), byref(out), byref(err)))
+        return MPO(self, out, U.L), err.value
 
     def mpo_apply_batched(self, Us, vs, st: Strategy):
         n = len(vs)

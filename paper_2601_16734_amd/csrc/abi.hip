@@ -288,6 +288,26 @@ int smps_mps_read(smps_ctx* c, const smps_mps* m, int site, double* host_out, si
     return SMPS_OK;
 }
 
+int smps_mpo_shape(const smps_mpo* u, int* L, int* pout, int* pin, int* bonds) {
+    if (!u) return SMPS_EINVAL;
+    if (L) *L = u->L;
+    if (pout) std::memcpy(pout, u->pout.data(), sizeof(int) * u->L);
+    if (pin) std::memcpy(pin, u->pin.data(), sizeof(int) * u->L);
+    if (bonds) std::memcpy(bonds, u->bonds.data(), sizeof(int) * (u->L + 1));
+    return SMPS_OK;
+}
+
+int smps_mpo_read(smps_ctx* c, const smps_mpo* u, int site, double* host_out, size_t count) {
+    if (!c) return SMPS_EINVAL;
+    if (!u || !host_out) return fail(c, SMPS_EINVAL, "NULL argument");
+    if (site < 0 || site >= u->L) return fail(c, SMPS_EINVAL, "site out of range");
+    if (count != u->site_size(site)) return fail(c, SMPS_EINVAL, "count does not match the site size");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    SMPS_HIP(c, hipMemcpyAsync(host_out, u->data + u->off[site], 8 * count, hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipStreamSynchronize(c->stream));
+    return SMPS_OK;
+}
+
 int smps_mps_device_ptr(const smps_mps* m, int site, const double** ptr) {
     if (!m || !ptr || site < 0 || site >= m->L) return SMPS_EINVAL;
     *ptr = m->data + m->off[site];
@@ -450,6 +470,113 @@ int smps_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, 
     if (rc == SMPS_OK) rc = run_combine(c, n, w, ops.data(), v, *st, out, trunc_err);
     for (smps_mpo* I : owned) smps_mpo_destroy(I);
     return rc;
+}
+
+// Transposed operator (real arithmetic: the adjoint), for products from the right.
+int smps_mpo_transpose(smps_ctx* c, const smps_mpo* U, smps_mpo** out) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!U) return fail(c, SMPS_EINVAL, "NULL handle");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    smps_mpo* T = new smps_mpo();
+    T->ctx = c;
+    T->L = U->L;
+    T->pout = U->pin;
+    T->pin = U->pout;
+    T->bonds = U->bonds;
+    T->off = U->off;  // same site sizes
+    T->bytes = U->bytes;
+    T->data = (double*)dev_alloc(c, T->bytes);
+    if (!T->data) {
+        delete T;
+        return fail(c, SMPS_ENOMEM, "MPO allocation failed");
+    }
+    for (int k = 0; k < U->L; ++k) {
+        const hipError_t e = launch_mpo_site_transpose(U->data + U->off[k], T->data + T->off[k], U->bonds[k],
+                                                       U->pout[k], U->pin[k], U->bonds[k + 1], c->stream);
+        if (e != hipSuccess) {
+            smps_mpo_destroy(T);
+            return fail(c, SMPS_EHIP, std::string("transpose: ") + hipGetErrorString(e));
+        }
+    }
+    *out = T;
+    return SMPS_OK;
+}
+
+// v @ U (Sec. 2.4.2): the operator applied from the right, U^T v in real arithmetic.
+int smps_mpo_apply_right(smps_ctx* c, const smps_mps* v, const smps_mpo* U, const smps_strategy* st,
+                         smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    smps_mpo* T = nullptr;
+    int rc = smps_mpo_transpose(c, U, &T);
+    if (rc) return rc;
+    rc = smps_mpo_apply(c, T, v, st, out, trunc_err);
+    smps_mpo_destroy(T);
+    return rc;
+}
+
+// Sequential application of a list of operators, compressing after each
+// product (Sec. 2.4.3): U[n-1] ... U[1] U[0] v.
+int smps_mpo_list_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* v, const smps_strategy* st,
+                        smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !U || !v) return fail(c, SMPS_EINVAL, "an operator list needs n >= 1 operators and a state");
+    const smps_mps* cur = v;
+    smps_mps* owned = nullptr;
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        smps_mps* next = nullptr;
+        double err = 0.0;
+        const int rc = smps_mpo_apply(c, U[i], cur, st, &next, &err);
+        if (owned) smps_mps_destroy(owned);
+        if (rc) return rc;
+        owned = next;
+        cur = next;
+        total += err;
+    }
+    if (trunc_err) *trunc_err = total;
+    *out = owned;
+    return SMPS_OK;
+}
+
+// Compression of an operator (the paper's simplify_mpo, Sec. 2.4.1): the MPO
+// read as an MPS whose site space is (out, in) is compressed by simplify.
+int smps_mpo_simplify(smps_ctx* c, const smps_mpo* U, const smps_strategy* st, smps_mpo** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!U) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    SMPS_HIP(c, hipSetDevice(c->device));
+    std::vector<int> phys(U->L);
+    for (int k = 0; k < U->L; ++k) phys[k] = U->pout[k] * U->pin[k];
+    smps_mps* m = new_mps(c, U->L, phys, U->bonds);
+    if (!m) return fail(c, SMPS_ENOMEM, "allocation failed");
+    SMPS_HIP(c, hipMemcpyAsync(m->data, U->data, U->bytes, hipMemcpyDeviceToDevice, c->stream));
+    smps_mps* r = nullptr;
+    rc = smps_simplify(c, m, st, &r, trunc_err);
+    smps_mps_destroy(m);
+    if (rc) return rc;
+    smps_mpo* T = new smps_mpo();
+    T->ctx = c;
+    T->L = U->L;
+    T->pout = U->pout;
+    T->pin = U->pin;
+    T->bonds = r->bonds;
+    T->off = r->off;
+    T->bytes = r->bytes;
+    T->data = r->data;  // the MPS storage becomes the operator's
+    r->data = nullptr;
+    r->bytes = 0;
+    smps_mps_destroy(r);
+    *out = T;
+    return SMPS_OK;
 }
 
 int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,

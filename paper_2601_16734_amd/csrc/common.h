@@ -171,6 +171,7 @@ hipError_t launch_sumsq(const double* x, const int* dims, DimExpr n, int n_cap, 
 hipError_t launch_check_finite(const double* x, const int* dims, DimExpr n, int n_cap, int* status,
                                hipStream_t s);
 hipError_t launch_convert_f32_f64(const float* src, double* dst, size_t n, hipStream_t s);
+hipError_t launch_mpo_site_transpose(const double* src, double* dst, int Dl, int o, int i, int Dr, hipStream_t s);
 // y = a x + b y over m * n doubles (m, n from dims)
 hipError_t launch_axpby(double* y, const double* x, double a, double b, const int* dims, DimExpr m, DimExpr n,
                         int cap, hipStream_t s);

@@ -214,4 +214,27 @@ hipError_t launch_axpby(double* y, const double* x, double a, double b, const in
     return hipGetLastError();
 }
 
+// dst[b][i][o][b'] = src[b][o][i][b'] (one MPO site, Dl x o x i x Dr)
+__global__ void mpo_site_transpose_kernel(const double* src, double* dst, int Dl, int o, int i, int Dr) {
+    const long long n = (long long)Dl * o * i * Dr;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        long long r = e;
+        const int br = (int)(r % Dr);
+        r /= Dr;
+        const int ii = (int)(r % i);
+        r /= i;
+        const int oo = (int)(r % o);
+        const int bl = (int)(r / o);
+        dst[(((long long)bl * i + ii) * o + oo) * Dr + br] = src[e];
+    }
+}
+
+hipError_t launch_mpo_site_transpose(const double* src, double* dst, int Dl, int o, int i, int Dr, hipStream_t s) {
+    const long long n = (long long)Dl * o * i * Dr;
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long long>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(mpo_site_transpose_kernel, dim3(blocks), dim3(256), 0, s, src, dst, Dl, o, i, Dr);
+    return hipGetLastError();
+}
+
 }  // namespace smps
