@@ -485,3 +485,31 @@ def test_combination_is_linear_in_the_weights():
     assert a.ranks == b.ranks
     f = om.scprod(a.mps, b.mps) / (a.norm * b.norm)
     assert abs(1 - f) <= 1e-12 and abs(a.norm - b.norm) <= 1e-12 * b.norm
+
+
+# ---- two-site DMRG (Sec. 3.1.1) -----------------------------------------------
+
+def test_dmrg_xx_chain_matches_free_fermions():
+    from oracle import dmrg as od
+    L = 8
+    H = synth.xxz_mpo(np.ones(L - 1), np.zeros(L - 1))
+    guess = synth.random_mps(np.random.default_rng(60), L, 2, 4)
+    E, psi, _ = od.dmrg(H, guess, max_bond=16, tol=0.0, sweeps=4)
+    assert abs(E - od.xx_chain_ground_energy(1.0, L)) <= 1e-10 * abs(E)
+
+
+def test_dmrg_matches_dense_ground_state():
+    from oracle import dmrg as od
+    L = 8
+    rng = np.random.default_rng(61)
+    H = synth.xxz_mpo(rng.uniform(0.5, 1.5, L - 1), rng.uniform(0.5, 1.5, L - 1))
+    guess = synth.random_mps(rng, L, 2, 3)
+    E, psi, energies = od.dmrg(H, guess, max_bond=16, tol=0.0, sweeps=4)
+    Hd = dense.mpo_to_dense(H)
+    e0 = np.linalg.eigvalsh(Hd)[0]
+    assert abs(E - e0) <= 1e-10 * abs(e0)
+    v = dense.mps_to_dense(psi)
+    assert abs(np.linalg.norm(v) - 1.0) <= 1e-12
+    assert np.linalg.norm(Hd @ v - E * v) <= 1e-8 * abs(E)
+    # the energy never rises along the sweep (variational, nothing truncated)
+    assert all(b <= a + 1e-10 * abs(a) for a, b in zip(energies, energies[1:]))
