@@ -217,6 +217,23 @@ int smps_mpo_list_apply(smps_ctx *ctx, int n, const smps_mpo *const *U, const sm
 int smps_mpo_simplify(smps_ctx *ctx, const smps_mpo *U, const smps_strategy *strategy, smps_mpo **out,
                       double *trunc_err);
 
+/* Ground-state search by two-site DMRG (Sec. 3.1.1).  H: a real symmetric
+ * operator with pout == pin == the guess's physical dimensions.  guess: any
+ * nonzero MPS of that shape (not modified; it is right-canonicalised and
+ * normalised on a copy).  Each two-site update finds the lowest eigenpair of
+ * the effective operator L[k] W_k W_{k+1} R[k+2] by Lanczos with at most
+ * krylov_dim vectors (2..128; full re-orthogonalisation), then splits the pair
+ * with the exact SVD under the strategy's max_bond / tol / trunc_mode.  A sweep
+ * is a left-to-right and a right-to-left pass; strategy->max_sweeps sweeps run,
+ * or fewer when sweep_tol > 0 and the relative change of the energy over a
+ * sweep falls below it.  The computation is FP64 throughout (precision and
+ * factorization must be SMPS_PREC_FP64 / SMPS_FACT_SVD).  On success *out (caller owns it)
+ * is the normalised state with isometry centre 0 and *energy the Ritz value of
+ * the last update.  Two-site tensors with more than 2048 rows or columns are
+ * rejected with SMPS_EUNSUPPORTED. */
+int smps_dmrg(smps_ctx *ctx, const smps_mpo *H, const smps_mps *guess, const smps_strategy *strategy,
+              int krylov_dim, smps_mps **out, double *energy);
+
 /* Batched apply: n independent (U[i], v[i]) problems of arbitrary length and
    bonds under one strategy, advanced together bond step by bond step; the
    launch sequence is captured once in a HIP graph per batch shape and replayed.

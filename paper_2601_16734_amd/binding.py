@@ -35,7 +35,7 @@ EXPORTS = [
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
-    "smps_autotune_entries",
+    "smps_autotune_entries", "smps_dmrg",
 ]
 
 
@@ -113,6 +113,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_autotune_load": (c_int, [vp, ctypes.c_char_p]),
         "smps_autotune_clear": (c_int, [vp]),
         "smps_autotune_entries": (c_int, [vp, ip]),
+        "smps_dmrg": (c_int, [vp, vp, vp, POINTER(Strategy), c_int, POINTER(vp), dp]),
         "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
                                        POINTER(c_float), c_int]),
     }
@@ -332,6 +333,13 @@ class Context:
         err = c_double()
         self._check(self.lib.smps_mpo_simplify(self.h, U.h, byref(st), byref(out), byref(err)))
         return MPO(self, out, U.L), err.value
+
+    def dmrg(self, H: "MPO", guess: MPS, st: Strategy, krylov_dim: int = 24):
+        """Two-site DMRG ground-state search (Sec. 3.1.1); returns (state, energy)."""
+        out = c_void_p()
+        e = c_double()
+        self._check(self.lib.smps_dmrg(self.h, H.h, guess.h, byref(st), int(krylov_dim), byref(out), byref(e)))
+        return MPS(self, out), e.value
 
     def mpo_apply_batched(self, Us, vs, st: Strategy):
         n = len(vs)

@@ -579,6 +579,26 @@ int smps_mpo_simplify(smps_ctx* c, const smps_mpo* U, const smps_strategy* st, s
     return SMPS_OK;
 }
 
+int smps_dmrg(smps_ctx* c, const smps_mpo* H, const smps_mps* guess, const smps_strategy* st, int krylov_dim,
+              smps_mps** out, double* energy) {
+    if (!c) return SMPS_EINVAL;
+    if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!H || !guess) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    if (st->precision != SMPS_PREC_FP64 || st->factorization != SMPS_FACT_SVD)
+        return fail(c, SMPS_EUNSUPPORTED, "DMRG runs in FP64 with the exact factorization");
+    if (krylov_dim < 2 || krylov_dim > 128) return fail(c, SMPS_EINVAL, "krylov_dim must be in 2..128");
+    if (H->L != guess->L) return fail(c, SMPS_EINVAL, "operator and guess lengths differ");
+    if (guess->L < 2) return fail(c, SMPS_EUNSUPPORTED, "DMRG needs at least two sites");
+    for (int k = 0; k < H->L; ++k)
+        if (H->pout[k] != guess->phys[k] || H->pin[k] != guess->phys[k])
+            return fail(c, SMPS_EINVAL, "operator site dimensions must equal the guess's");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    return run_dmrg(c, H, guess, *st, krylov_dim, out, energy);
+}
+
 int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                            const smps_strategy* st, smps_mps** out, double* trunc_err) {
     if (!c) return SMPS_EINVAL;

@@ -90,6 +90,9 @@ int run_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_stra
 int run_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
                 const smps_strategy& st, smps_mps** out, double* trunc_err);
 void mlp_free(smps_ctx* c);
+// two-site DMRG ground-state search (dmrg.hip)
+int run_dmrg(smps_ctx* c, const smps_mpo* H, const smps_mps* guess, const smps_strategy& st, int krylov,
+             smps_mps** out, double* energy);
 // GEMM tile autotuning (autotune.hip / sweep.hip)
 int tune_gemm_shape(smps_ctx* c, int prec, int a_type, int b_type, int c_type, int ta, int tb, int tc, int M, int N,
                     int K, int reps, int* best_out);
