@@ -44,6 +44,9 @@ def parse():
                     help="only measure the learned-rank randomized factorization (train the predictor on the "
                          "n=10 / n=20 / L=100 workloads' spectra, evaluate on the L=64 chi=512 decaying-spectrum "
                          "workload and on a tolerance-bound one) and print its JSON line")
+    ap.add_argument("--dmrg", default="", metavar="L,L,...",
+                    help="only measure the two-site DMRG ground-state search of the critical transverse-field "
+                         "Ising chain (-sum ZZ - sum X) at these chain lengths and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -147,6 +150,72 @@ def learned_rank(args):
     ctx.close()
 
 
+def dmrg_leg(args):
+    """Ground-state search of -sum Z_i Z_{i+1} - sum X_i (open chain) from a
+    random bond-4 guess, relative tolerance eps^2 / (n - 1) with eps = 1e-6 on
+    the discarded weight, bond cap 256, Krylov dimension 24, sweeps until the
+    energy changes by less than 1e-13 (relative) over a sweep.  The time of a
+    whole search (inputs resident, one warm-up search first) is reported with
+    its two-site updates per second."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    sizes = [int(x) for x in args.dmrg.split(",")]
+    res = {}
+    for L in sizes:
+        H = ctx.mpo_create(synth.tfim_mpo(L, 1.0, 1.0))
+        g = ctx.mps_create(synth.random_mps(np.random.default_rng(70), L, 2, 4))
+        st = B.strategy(256, 1e-12 / (L - 1), sweeps=10, sweep_tol=1e-13)
+        psi, E = ctx.dmrg(H, g, st)  # warm-up
+        psi.destroy()
+        times = []
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            psi, E = ctx.dmrg(H, g, st)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            bonds = psi.shape()[1]
+            psi.destroy()
+        info = ctx.last_info()
+        dt = float(np.median(times))
+        res[L] = {"seconds": dt, "energy": E, "sweeps": info["sweeps_done"], "site_updates": info["steps"],
+                  "site_updates_per_s": info["steps"] / dt, "max_bond": max(bonds)}
+        print(f"L={L}: {dt * 1e3:.1f} ms, {info['sweeps_done']} sweeps, {info['steps']} updates, "
+              f"chi {max(bonds)}", file=sys.stderr, flush=True)
+    out = {"metric": "DMRG two-site updates/s, critical Ising chain ground state", "unit": "site-updates/s",
+           "dtype": "f64", "data": "synthetic", "steps": max(1, args.steps),
+           "config": {"workload": "dmrg_tfim_critical", "J": 1.0, "h": 1.0, "eps": 1e-6, "bond_cap": 256,
+                      "krylov_dim": 24, "sweep_tol": 1e-13},
+           "per_L": {str(L): r for L, r in res.items()}}
+    if not args.no_cpu:
+        # CPU oracle (dense local eigensolver) and the closed-form energies
+        from oracle import dmrg as od
+        for L, r in res.items():
+            ex = od.tfim_ground_energy(L, 1.0, 1.0)
+            r["exact_energy"] = ex
+            r["rel_energy_error"] = (r["energy"] - ex) / abs(ex)
+        L = 16
+        t = time.perf_counter()
+        _, _, en = od.dmrg(synth.tfim_mpo(L, 1.0, 1.0), synth.random_mps(np.random.default_rng(70), L, 2, 4),
+                           max_bond=256, tol=1e-12 / (L - 1), sweeps=2)
+        dt = time.perf_counter() - t
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        out["cpu_baseline"] = {"value": len(en) / dt, "unit": "site-updates/s", "cores": int(cores),
+                               "kind": "oracle", "sample": f"oracle DMRG, L={L}, 2 sweeps ({len(en)} updates)"}
+    print(json.dumps(out))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -158,6 +227,9 @@ def main():
         return
     if args.a11:
         learned_rank(args)
+        return
+    if args.dmrg:
+        dmrg_leg(args)
         return
 
     import numpy as np

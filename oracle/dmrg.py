@@ -71,3 +71,21 @@ def xx_chain_ground_energy(J: float, L: int) -> float:
     state fills every negative level."""
     eps = 4.0 * J * np.cos(np.arange(1, L + 1) * np.pi / (L + 1))
     return float(np.sum(eps[eps < 0]))
+
+
+def tfim_ground_energy(L: int, J: float = 1.0, h: float = 1.0) -> float:
+    """Closed form for H = -J sum Z_i Z_{i+1} - h sum X_i, open chain
+    (Lieb, Schultz & Mattis 1961; Pfeuty 1970).  With Majorana operators
+    a_i, b_i of the Jordan-Wigner fermions, X_i = -i a_i b_i and
+    Z_i Z_{i+1} = -i b_i a_{i+1}, so H = (i/4) gamma^T A gamma with A real
+    antisymmetric and tridiagonal along (a_1, b_1, a_2, ..., b_L), its
+    off-diagonal entries alternating 2h (within a site) and 2J (between sites).
+    The ground energy is -1/4 of the sum of the absolute eigenvalues of iA;
+    on this path graph a diagonal sign change maps A to the symmetric
+    tridiagonal matrix with the same off-diagonal magnitudes, so those are its
+    absolute eigenvalues."""
+    off = np.empty(2 * L - 1)
+    off[0::2] = 2.0 * h
+    off[1::2] = 2.0 * J
+    ev = scipy.linalg.eigh_tridiagonal(np.zeros(2 * L), off, eigvals_only=True)
+    return float(-0.25 * np.sum(np.abs(ev)))

@@ -46,6 +46,51 @@ __global__ void transpose_kernel(const double* A, double* B, int rows, int cols)
     }
 }
 
+// h[i] = <V_i, w> for the rows i < rows of V (row stride n): one workgroup per
+// row, fixed summation order
+__global__ __launch_bounds__(256) void multidot_kernel(const double* V, long long n, const double* w, double* h) {
+    __shared__ double part[256];
+    const double* v = V + (long long)blockIdx.x * n;
+    double a = 0.0;
+    for (long long x = threadIdx.x; x < n; x += 256) a = fma(v[x], w[x], a);
+    part[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) h[blockIdx.x] = part[0];
+}
+
+// w -= sum_{i < rows} h[i] V_i (coalesced along the vector)
+__global__ void project_out_kernel(const double* V, long long n, int rows, const double* h, double* w) {
+    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x) {
+        double a = w[x];
+        for (int i = 0; i < rows; ++i) a = fma(-h[i], V[(long long)i * n + x], a);
+        w[x] = a;
+    }
+}
+
+// w = sum_{i < rows} y[i] V_i
+__global__ void combine_rows_kernel(const double* V, long long n, int rows, const double* y, double* w) {
+    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x) {
+        double a = 0.0;
+        for (int i = 0; i < rows; ++i) a = fma(y[i], V[(long long)i * n + x], a);
+        w[x] = a;
+    }
+}
+
+// dst = src / sqrt(*nrm2); zero when the norm is at most rel * |*ref| (ref
+// non-NULL: Lanczos breakdown) or not positive
+__global__ void normalize_kernel(const double* src, double* dst, long long n, const double* nrm2, const double* ref,
+                                 double rel) {
+    const double b = sqrt(fmax(*nrm2, 0.0));
+    const bool zero = !(b > 1e-300) || (ref && !(b > rel * fabs(*ref)));
+    const double inv = zero ? 0.0 : 1.0 / b;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i] * inv;
+}
+
 __global__ void scale_kernel(double* x, double a, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         x[i] *= a;
@@ -112,6 +157,12 @@ struct Dmrg {
     double *theta = nullptr, *V = nullptr, *w = nullptr, *x1 = nullptr, *x2 = nullptr, *x3 = nullptr;
     double *jx = nullptr, *Q = nullptr, *sigma = nullptr, *scal = nullptr, *fro2 = nullptr, *tmp = nullptr;
     int* ints = nullptr;  // [rank, status, flag, perm...]
+    double* hc = nullptr;    // Lanczos coefficients: 2 (m+1)^2 projections, m+1 |w|^2, m+1 Ritz weights
+    double* host = nullptr;  // pinned staging of hc
+    int* host_ints = nullptr;  // pinned staging of the factorization's rank and status
+    static constexpr double BREAKDOWN = 1e-12;  // beta <= BREAKDOWN |alpha|: invariant subspace found
+    static constexpr double RESIDUAL = 1e-11;   // stop once beta_j |y_j| <= RESIDUAL |E|
+    int first_chunk = 8, chunk = 4;
     std::vector<void*> allocs;
     double energy = 0.0;
     int status_seen = 0;  // factorization status that stopped the run
@@ -225,7 +276,7 @@ struct Dmrg {
         jd.floor_eps = 2.220446049250313e-16;
         hipError_t e = launch_jacobi(jd, nv, ln, nullptr, ints + 2, s);
         if (e != hipSuccess) return e;
-        int h[2] = {0, 0};
+        int* h = host_ints;
         e = hipMemcpyAsync(h, ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
@@ -272,64 +323,82 @@ struct Dmrg {
 
     // Lanczos with full re-orthogonalisation (two Gram-Schmidt passes by GEMMs)
     // on the pair tensor in theta; theta is replaced by the lowest Ritz vector.
+    // The recurrence runs on the device: the projections of pass 1 and pass 2
+    // of iteration j land in row j of hc[0] / hc[1], |w|^2 in bn[j], and the next
+    // basis vector is normalised by a kernel reading bn[j] (zero on breakdown).
+    // The host reads the coefficients once per chunk of iterations (pinned),
+    // solves the small tridiagonal problem and stops when the Ritz residual
+    // beta_j |y_j| is small or the Krylov space is exhausted.
     hipError_t lanczos(int k) {
         const long long n = (long long)chi[k] * d[k] * d[k + 1] * chi[k + 2];
-        const int mm_max = (int)std::min<long long>(m, n);
-        double nrm2 = 0.0;
-        hipError_t e = dot(theta, theta, n, &nrm2);
+        const int mmax = (int)std::min<long long>(m, n);
+        const int ld = m + 1;
+        double* hc0 = hc;
+        double* hc1 = hc + (size_t)ld * ld;
+        double* bn = hc + 2 * (size_t)ld * ld;
+        hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, s, theta, theta, n, scal);
+        hipLaunchKernelGGL(normalize_kernel, dim3(blocks_for(n)), dim3(256), 0, s, theta, V, n, scal,
+                           (const double*)nullptr, 0.0);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (!(nrm2 > 0.0)) return hipErrorInvalidValue;
-        e = hipMemcpyAsync(V, theta, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-        e = scale(V, 1.0 / std::sqrt(nrm2), n);
-        if (e != hipSuccess) return e;
-        std::vector<double> T((size_t)mm_max * mm_max, 0.0), h(mm_max + 1);
-        int j = 0;
-        for (; j < mm_max; ++j) {
-            double* vj = V + (size_t)j * n;
-            e = matvec(k, vj, w);
-            if (e != hipSuccess) return e;
-            for (int pass = 0; pass < 2; ++pass) {
-                // h = V[0..j] w, w -= V[0..j]^T h
-                e = mm(V, w, tmp, j + 1, 1, (int)n, 0, 0);
-                if (e != hipSuccess) return e;
-                e = hipMemcpyAsync(h.data(), tmp, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s);
-                if (e != hipSuccess) return e;
-                e = hipStreamSynchronize(s);
-                if (e != hipSuccess) return e;
-                if (pass == 0) T[(size_t)j * mm_max + j] = h[j];
-                e = mm(V, tmp, w, (int)n, 1, j + 1, 1, 0, -1.0, 1.0);
-                if (e != hipSuccess) return e;
-            }
-            double b2 = 0.0;
-            e = dot(w, w, n, &b2);
-            if (e != hipSuccess) return e;
-            const double beta = std::sqrt(std::max(0.0, b2));
-            if (j + 1 == mm_max || beta <= 1e-12 * std::fabs(T[(size_t)j * mm_max + j]) + 1e-300) {
-                ++j;
-                break;
-            }
-            T[(size_t)j * mm_max + j + 1] = T[(size_t)(j + 1) * mm_max + j] = beta;
-            double* vn = V + (size_t)(j + 1) * n;
-            e = hipMemcpyAsync(vn, w, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return e;
-            e = scale(vn, 1.0 / beta, n);
-            if (e != hipSuccess) return e;
-        }
-        const int mk = j;
-        std::vector<double> Tk((size_t)mk * mk);
-        for (int a = 0; a < mk; ++a)
-            for (int b = 0; b < mk; ++b) Tk[(size_t)a * mk + b] = T[(size_t)a * mm_max + b];
+        int j = 0, mk = 0;
         std::vector<double> y;
-        energy = smallest_eigenpair(Tk, mk, y);
+        bool done = false;
+        while (!done) {
+            const int j1 = std::min(mmax, j + (j == 0 ? first_chunk : chunk));
+            for (; j < j1; ++j) {
+                const double* vj = V + (size_t)j * n;
+                e = matvec(k, vj, w);
+                if (e != hipSuccess) return e;
+                for (int pass = 0; pass < 2; ++pass) {
+                    double* h = (pass ? hc1 : hc0) + (size_t)j * ld;
+                    hipLaunchKernelGGL(multidot_kernel, dim3(j + 1), dim3(256), 0, s, V, n, w, h);
+                    hipLaunchKernelGGL(project_out_kernel, dim3(blocks_for(n)), dim3(256), 0, s, V, n, j + 1, h, w);
+                    e = hipGetLastError();
+                    if (e != hipSuccess) return e;
+                }
+                hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, s, w, w, n, bn + j);
+                hipLaunchKernelGGL(normalize_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w, V + (size_t)(j + 1) * n,
+                                   n, bn + j, hc0 + (size_t)j * ld + j, BREAKDOWN);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
+            const size_t nb = (2 * (size_t)ld * ld + ld) * sizeof(double);
+            e = hipMemcpyAsync(host, hc, nb, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return e;
+            const double* h0 = host;
+            const double* hb = host + 2 * (size_t)ld * ld;
+            // Krylov size: up to the first breakdown (the same test as the kernel's)
+            mk = j;
+            for (int i = 0; i < j; ++i) {
+                const double b = std::sqrt(std::max(0.0, hb[i]));
+                if (!(b > BREAKDOWN * std::fabs(h0[(size_t)i * ld + i])) || !(b > 1e-300)) {
+                    mk = i + 1;
+                    done = true;
+                    break;
+                }
+            }
+            std::vector<double> T((size_t)mk * mk, 0.0);
+            for (int i = 0; i < mk; ++i) {
+                T[(size_t)i * mk + i] = h0[(size_t)i * ld + i];
+                if (i + 1 < mk) T[(size_t)i * mk + i + 1] = T[(size_t)(i + 1) * mk + i] = std::sqrt(hb[i]);
+            }
+            energy = smallest_eigenpair(T, mk, y);
+            const double resid = std::sqrt(std::max(0.0, hb[mk - 1])) * std::fabs(y[mk - 1]);
+            if (j >= mmax || resid <= RESIDUAL * std::max(std::fabs(energy), 1e-300)) done = true;
+        }
         // theta = V^T y, normalised
-        e = hipMemcpyAsync(tmp, y.data(), sizeof(double) * mk, hipMemcpyHostToDevice, s);
+        double* yd = hc + 2 * (size_t)ld * ld + ld;
+        std::memcpy(host, y.data(), sizeof(double) * mk);
+        e = hipMemcpyAsync(yd, host, sizeof(double) * mk, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        e = mm(V, tmp, theta, (int)n, 1, mk, 1, 0);
-        if (e != hipSuccess) return e;
-        e = dot(theta, theta, n, &nrm2);
-        if (e != hipSuccess) return e;
-        return scale(theta, 1.0 / std::sqrt(nrm2), n);
+        hipLaunchKernelGGL(combine_rows_kernel, dim3(blocks_for(n)), dim3(256), 0, s, V, n, mk, yd, w);
+        hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(1024), 0, s, w, w, n, scal);
+        hipLaunchKernelGGL(normalize_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w, theta, n, scal,
+                           (const double*)nullptr, 0.0);
+        return hipGetLastError();
     }
 
     hipError_t step(int k, bool left_to_right) {
@@ -413,8 +482,16 @@ struct Dmrg {
              (w = alloc<double>(nth)) && (x1 = alloc<double>(nx)) && (x2 = alloc<double>(nx)) &&
              (x3 = alloc<double>(nx)) && (jx = alloc<double>(nth)) && (Q = alloc<double>(nth)) &&
              (sigma = alloc<double>(nvmax)) && (scal = alloc<double>(1)) && (fro2 = alloc<double>(1)) &&
-             (tmp = alloc<double>(std::max<size_t>(nth, (size_t)m + 1))) && (ints = alloc<int>(3 + (size_t)nvmax));
+             (tmp = alloc<double>(std::max<size_t>(nth, (size_t)m + 1))) && (ints = alloc<int>(3 + (size_t)nvmax)) &&
+             (hc = alloc<double>(2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)));
         if (!ok) return fail(c, SMPS_ENOMEM, "DMRG workspace allocation failed");
+        {
+            const size_t hb = (2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)) * sizeof(double);
+            int rc = ensure_pinned(c, hb + 64);
+            if (rc) return rc;
+            host = (double*)c->pinned;
+            host_ints = (int*)(c->pinned + hb);
+        }
         for (int k = 0; k < L; ++k)
             SMPS_HIP(c, hipMemcpyAsync(psi[k], guess->data + guess->off[k], 8 * guess->site_size(k),
                                        hipMemcpyDeviceToDevice, s));

@@ -3,8 +3,8 @@
 This module only *draws* or *writes down* input tensors: random MPS/MPO site
 tensors, and the closed-form operators and states the paper builds by
 construction (finite-difference shift / Laplacian MPOs of Sec. 5.1, the
-bond-2 sine and bond-1 exponential states of Sec. 4.2, a nearest-neighbour
-XXZ-type Hamiltonian MPO).  It contains none of the compression arithmetic:
+bond-2 sine and bond-1 exponential states of Sec. 4.2, nearest-neighbour
+XXZ-type and transverse-field Ising Hamiltonian MPOs).  It contains none of the compression arithmetic:
 no contraction, no factorization, no truncation.  Both the CPU oracle and the
 GPU library consume exactly the arrays produced here.
 
@@ -186,6 +186,31 @@ def xxz_mpo(Jxy: np.ndarray, Jz: np.ndarray) -> list[np.ndarray]:
 # ---------------------------------------------------------------------------
 # Closed-form states (Sec. 4.2: sums of exponentials)
 # ---------------------------------------------------------------------------
+
+def tfim_mpo(L: int, J: float = 1.0, h: float = 1.0) -> list[np.ndarray]:
+    """Transverse-field Ising chain of the DMRG example (Sec. 10.1), open ends:
+    H = -J sum_i Z_i Z_{i+1} - h sum_i X_i (Pauli matrices), written as the
+    D = 3 operator with rows/columns (done, pending Z, start).  The example's
+    formula is J = h = 1; its code listing uses Z/2 and X/2 with unit
+    prefactors, i.e. J = 1/4, h = 1/2."""
+    I = np.eye(2)
+    Z = np.diag([1.0, -1.0])
+    X = np.array([[0.0, 1.0], [1.0, 0.0]])
+    out = []
+    for k in range(L):
+        W = np.zeros((3, 2, 2, 3))
+        W[0, :, :, 0] = I
+        W[0, :, :, 1] = Z
+        W[0, :, :, 2] = -h * X
+        W[1, :, :, 2] = -J * Z
+        W[2, :, :, 2] = I
+        if k == 0:
+            W = W[0:1]
+        if k == L - 1:
+            W = W[..., 2:3]
+        out.append(np.ascontiguousarray(W))
+    return out
+
 
 def sine_mps(n: int, a: float, dx: float) -> list[np.ndarray]:
     """Bond-2 MPS of v_i = sin(a + i dx), i MSB-first on n sites."""

@@ -75,6 +75,32 @@ def test_longer_chain_against_closed_form(ctx):
     assert abs(ctx.norm(psi) - 1.0) <= 1e-12
 
 
+@pytest.mark.parametrize("L", [16, 64])
+def test_critical_ising_chain_at_the_benchmark_tolerance(ctx, L):
+    # -sum ZZ - sum X at the benchmark's relative tolerance eps^2 / (n - 1),
+    # eps = 1e-6, bond left free (cap 256), early exit on the energy
+    H = synth.tfim_mpo(L, 1.0, 1.0)
+    guess = synth.random_mps(np.random.default_rng(70), L, 2, 4)
+    st = B.strategy(256, 1e-12 / (L - 1), sweeps=8, sweep_tol=1e-13)
+    psi, E = ctx.dmrg(ctx.mpo_create(H), ctx.mps_create(guess), st)
+    exact = od.tfim_ground_energy(L, 1.0, 1.0)
+    info = ctx.last_info()
+    print("tfim", L, E, exact, (E - exact) / abs(exact), max(psi.shape()[1]), info["sweeps_done"], flush=True)
+    assert E >= exact - 1e-11 * abs(exact)
+    assert abs(E - exact) <= 1e-10 * abs(exact)
+    assert info["sweeps_done"] < 8
+
+
+def test_ising_chain_of_the_code_listing(ctx):
+    # Z/2 and X/2 with unit prefactors: J = 1/4, h = 1/2
+    L = 10
+    H = synth.tfim_mpo(L, 0.25, 0.5)
+    guess = synth.random_mps(np.random.default_rng(71), L, 2, 2)
+    psi, E = ctx.dmrg(ctx.mpo_create(H), ctx.mps_create(guess), B.strategy(32, 0.0, sweeps=4))
+    exact = od.tfim_ground_energy(L, 0.25, 0.5)
+    assert abs(E - exact) <= 1e-12 * abs(exact)
+
+
 def test_bad_arguments_are_rejected(ctx):
     H = ctx.mpo_create(synth.xxz_mpo(np.ones(3), np.zeros(3)))
     v = ctx.mps_create(synth.random_mps(np.random.default_rng(64), 4, 2, 2))

@@ -513,3 +513,23 @@ def test_dmrg_matches_dense_ground_state():
     assert np.linalg.norm(Hd @ v - E * v) <= 1e-8 * abs(E)
     # the energy never rises along the sweep (variational, nothing truncated)
     assert all(b <= a + 1e-10 * abs(a) for a, b in zip(energies, energies[1:]))
+
+
+def test_tfim_closed_form_matches_dense_spectrum():
+    # the free-fermion formula against dense diagonalisation, and its two
+    # one-term limits (-h X per site; -J ZZ per bond) done by hand
+    from oracle import dmrg as od
+    for L, J, h in [(1, 1.0, 1.0), (3, 1.0, 1.0), (6, 0.25, 0.5), (9, 1.0, 0.3), (10, 0.7, 1.9)]:
+        e0 = np.linalg.eigvalsh(dense.mpo_to_dense(synth.tfim_mpo(L, J, h)))[0]
+        assert abs(od.tfim_ground_energy(L, J, h) - e0) <= 1e-12 * abs(e0)
+    assert abs(od.tfim_ground_energy(7, 0.0, 1.3) - (-7 * 1.3)) <= 1e-12
+    assert abs(od.tfim_ground_energy(7, 0.8, 0.0) - (-6 * 0.8)) <= 1e-12
+
+
+def test_dmrg_tfim_matches_closed_form():
+    from oracle import dmrg as od
+    L = 10
+    H = synth.tfim_mpo(L, 1.0, 1.0)
+    guess = synth.random_mps(np.random.default_rng(67), L, 2, 2)
+    E, _, _ = od.dmrg(H, guess, max_bond=32, tol=0.0, sweeps=3)
+    assert abs(E - od.tfim_ground_energy(L)) <= 1e-11 * abs(E)
