@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--dmrg", default="", metavar="L,L,...",
                     help="only measure the two-site DMRG ground-state search of the critical transverse-field "
                          "Ising chain (-sum ZZ - sum X) at these chain lengths and print its JSON line")
+    ap.add_argument("--diffusion", default="", metavar="N,N,...",
+                    help="only measure the RK4 integration of the diffusion equation (Gaussian initial state on "
+                         "2^N grid points, 1000 steps) and print its JSON line")
+    ap.add_argument("--rk4-steps", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -216,6 +220,93 @@ def dmrg_leg(args):
     ctx.close()
 
 
+def diffusion_leg(args):
+    """du/dt = nu d^2u/dx^2 on [-0.5, 0.5) with 2^n points, nu = 0.01, open
+    second-difference Laplacian, Gaussian initial condition (sigma = 0.1)
+    loaded densely and compressed on the device, RK4 steps of
+    dt = dx^2 / (20 nu), relative tolerance eps^2 / (n - 1) with eps = 1e-6 on
+    the discarded weight, up to 4 sweeps per compression with early exit.
+    Each RK4 step is one apply and four compressed linear combinations; the
+    timed region covers all the steps with the state resident on the device."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+    from paper_2601_16734_amd import evolution as EV
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    nu, steps = 0.01, args.rk4_steps
+    res, finals = {}, {}
+    for n in [int(x) for x in args.diffusion.split(",")]:
+        dx = 1.0 / 2 ** n
+        dt = dx * dx / (20.0 * nu)
+        lap = synth.laplacian_mpo(n, dx=dx)
+        lap[0] = nu * lap[0]
+        H = ctx.mpo_create(lap)
+        st = B.strategy(2 ** (n // 2), 1e-12 / (n - 1), sweeps=4, sweep_tol=1e-14)
+        exact = ctx.mps_create(synth.placement_mps(synth.gaussian_grid(n), n))
+        y0, _ = ctx.simplify(exact, st)
+        y = EV.rk4_step(ctx, H, y0, dt, st)  # warm-up
+        y.destroy()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        y = y0
+        for _ in range(steps):
+            y1 = EV.rk4_step(ctx, H, y, dt, st)
+            if y is not y0:
+                y.destroy()
+            y = y1
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        bonds = y.shape()[1]
+        finals[n] = (y.read(), dt)
+        y.destroy()
+        res[n] = {"seconds": sec, "rk4_steps": steps, "rk4_steps_per_s": steps / sec,
+                  "compressions_per_s": 5 * steps / sec, "max_bond": max(bonds), "dt": dt}
+        print(f"n={n}: {steps} RK4 steps in {sec:.2f} s ({steps / sec:.1f} steps/s), final bond {max(bonds)}",
+              file=sys.stderr, flush=True)
+    out = {"metric": "RK4 steps/s, diffusion equation on a quantized grid (apply + combinations + compression)",
+           "unit": "RK4 steps/s", "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "rk4_diffusion_gaussian", "nu": nu, "rk4_steps": steps, "eps": 1e-6,
+                      "dt": "dx^2/(20 nu)"},
+           "per_n": {str(n): r for n, r in res.items()}}
+    if not args.no_cpu:
+        # CPU oracle: dense RK4 of the same discrete system (accuracy) and the
+        # MPS-level RK4 step (baseline timing on a bounded sample)
+        from oracle import dense
+        from oracle import evolution as oe
+        for n, r in res.items():
+            if n > 12:
+                continue
+            sites, dt = finals[n]
+            lap = synth.laplacian_mpo(n, dx=1.0 / 2 ** n)
+            want = oe.dense_rk4(nu * dense.mpo_to_dense(lap), synth.gaussian_grid(n), dt, steps)
+            got = dense.mps_to_dense(sites)
+            r["rel_error_vs_dense_rk4"] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        n = min(res)
+        dx = 1.0 / 2 ** n
+        lap = synth.laplacian_mpo(n, dx=dx)
+        lap[0] = nu * lap[0]
+        from oracle import mps as om
+        y = om.simplify(synth.placement_mps(synth.gaussian_grid(n), n), 2 ** (n // 2), 1e-12 / (n - 1), 4).mps
+        k = 20
+        t = time.perf_counter()
+        for _ in range(k):
+            y = oe.rk4_step(lap, y, dx * dx / (20.0 * nu), 2 ** (n // 2), 1e-12 / (n - 1), sweeps=2)
+        sec = time.perf_counter() - t
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        out["cpu_baseline"] = {"value": k / sec, "unit": "RK4 steps/s", "cores": int(cores), "kind": "oracle",
+                               "sample": f"oracle RK4 step (2 sweeps per compression), n={n}, {k} steps"}
+    print(json.dumps(out))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -230,6 +321,9 @@ def main():
         return
     if args.dmrg:
         dmrg_leg(args)
+        return
+    if args.diffusion:
+        diffusion_leg(args)
         return
 
     import numpy as np

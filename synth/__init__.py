@@ -212,6 +212,42 @@ def tfim_mpo(L: int, J: float = 1.0, h: float = 1.0) -> list[np.ndarray]:
     return out
 
 
+def gaussian_grid(n: int, a: float = -0.5, b: float = 0.5, sigma: float = 0.1) -> np.ndarray:
+    """exp(-x^2 / (2 sigma^2)) sampled at x_i = a + i (b - a) / 2^n, i < 2^n: the
+    initial condition of the diffusion example (Sec. 10.3)."""
+    x = a + (b - a) / 2 ** n * np.arange(2 ** n)
+    return np.exp(-0.5 * (x / sigma) ** 2)
+
+
+def placement_mps(vec: np.ndarray, n: int) -> list[np.ndarray]:
+    """An exact MPS of a length-2^n vector (binary digits, most significant
+    first) built by index placement only: sites left of m = n // 2 copy the
+    digits seen so far into the bond (bond 2^k), sites right of m carry the
+    remaining digits from the right, and site m holds the entries of vec as a
+    (2^m, 2, 2^(n-1-m)) block.  Bond dimensions 2^min(k, n-k) at most; no
+    arithmetic is done on the values."""
+    vec = np.asarray(vec, dtype=np.float64)
+    assert vec.shape == (2 ** n,)
+    m = n // 2
+    out = []
+    for k in range(n):
+        if k < m:
+            A = np.zeros((2 ** k, 2, 2 ** (k + 1)))
+            for l in range(2 ** k):
+                for s in range(2):
+                    A[l, s, 2 * l + s] = 1.0
+        elif k == m:
+            A = vec.reshape(2 ** m, 2, 2 ** (n - 1 - m)).copy()
+        else:
+            r = 2 ** (n - 1 - k)
+            A = np.zeros((2 * r, 2, r))
+            for s in range(2):
+                for q in range(r):
+                    A[s * r + q, s, q] = 1.0
+        out.append(A)
+    return out
+
+
 def sine_mps(n: int, a: float, dx: float) -> list[np.ndarray]:
     """Bond-2 MPS of v_i = sin(a + i dx), i MSB-first on n sites."""
     th = [dx * 2.0 ** (n - 1 - k) for k in range(n)]

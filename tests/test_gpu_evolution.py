@@ -71,3 +71,41 @@ def test_euler_step(ctx):
     y = EV.euler_step(ctx, H, ctx.mps_create(y0), 0.1, B.strategy(64, 0.0, sweeps=2))
     want = vec + 0.1 * (Lap @ vec)
     assert np.linalg.norm(dense.mps_to_dense(y.read()) - want) <= 1e-11 * np.linalg.norm(want)
+
+
+def _diffusion_setup(ctx, n, nu=0.01):
+    dx = 1.0 / 2 ** n
+    dt = dx * dx / (20.0 * nu)
+    lap = synth.laplacian_mpo(n, dx=dx)
+    lap[0] = nu * lap[0]
+    return lap, dt
+
+
+def test_diffusion_benchmark_setting_matches_dense_rk4_and_oracle(ctx):
+    # Gaussian (sigma = 0.1) on 2^10 points of [-0.5, 0.5), nu = 0.01,
+    # dt = dx^2 / (20 nu), tolerance eps^2 / (n - 1), eps = 1e-6 (Sec. 10.3-10.4)
+    from oracle import evolution as oe
+    n = 10
+    lap, dt = _diffusion_setup(ctx, n)
+    tol = 1e-12 / (n - 1)
+    st = B.strategy(32, tol, sweeps=4, sweep_tol=1e-14)
+    v = synth.gaussian_grid(n)
+    y0, _ = ctx.simplify(ctx.mps_create(synth.placement_mps(v, n)), st)
+    assert np.linalg.norm(dense.mps_to_dense(y0.read()) - v) <= 1e-6 * np.linalg.norm(v)
+    H = ctx.mpo_create(lap)
+    y = y0
+    for i in range(20):
+        y = EV.rk4_step(ctx, H, y, dt, st)
+        if i == 1:
+            y2 = dense.mps_to_dense(y.read())
+    want = oe.dense_rk4(dense.mpo_to_dense(lap), v, dt, 20)
+    got = dense.mps_to_dense(y.read())
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("diffusion n=10, 20 steps: rel err vs dense RK4", err, flush=True)
+    assert err <= 1e-6
+    # two steps against the oracle's MPS-level RK4 from the same compressed start
+    yo = y0.read()
+    for _ in range(2):
+        yo = oe.rk4_step(lap, yo, dt, 32, tol, sweeps=4)
+    w2 = dense.mps_to_dense(yo)
+    assert np.linalg.norm(y2 - w2) <= 1e-9 * np.linalg.norm(w2)

@@ -533,3 +533,37 @@ def test_dmrg_tfim_matches_closed_form():
     guess = synth.random_mps(np.random.default_rng(67), L, 2, 2)
     E, _, _ = od.dmrg(H, guess, max_bond=32, tol=0.0, sweeps=3)
     assert abs(E - od.tfim_ground_energy(L)) <= 1e-11 * abs(E)
+
+
+# ---- diffusion workload inputs and the RK4 step (Sec. 7.1, Sec. 10.3) ---------
+
+def test_placement_mps_reproduces_the_vector_exactly():
+    rng = np.random.default_rng(80)
+    for n in range(1, 8):
+        v = rng.standard_normal(2 ** n)
+        mps = synth.placement_mps(v, n)
+        assert [t.shape[0] for t in mps][0] == 1 and mps[-1].shape[2] == 1
+        np.testing.assert_array_equal(dense.mps_to_dense(mps), v)
+
+
+def test_oracle_rk4_amplifies_a_laplacian_eigenvector_by_the_rk4_factor():
+    # v_i = sin((i + 1) dx), dx = pi / (N + 1), is an eigenvector of the open
+    # second-difference operator with eigenvalue -4 sin^2(dx / 2); one RK4 step
+    # multiplies it by 1 + z + z^2/2 + z^3/6 + z^4/24, z = lambda dt
+    from oracle import evolution as oe
+    n = 6
+    N = 2 ** n
+    dx = np.pi / (N + 1)
+    y0 = synth.sine_mps(n, dx, dx)
+    lam = -4.0 * np.sin(dx / 2) ** 2
+    dt = 0.3
+    z = lam * dt
+    R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    H = synth.laplacian_mpo(n)
+    y = y0
+    for _ in range(2):
+        y = oe.rk4_step(H, y, dt, max_bond=8, tol=0.0, sweeps=2)
+    want = R ** 2 * dense.mps_to_dense(y0)
+    assert np.max(np.abs(dense.mps_to_dense(y) - want)) <= 1e-12 * np.max(np.abs(want))
+    got_dense = oe.dense_rk4(dense.mpo_to_dense(H), dense.mps_to_dense(y0), dt, 2)
+    assert np.max(np.abs(got_dense - want)) <= 1e-12 * np.max(np.abs(want))
