@@ -183,6 +183,11 @@ int smps_last_log(const smps_ctx *ctx, int max_steps, double *deltas, int *ranks
    rejected and replaced by the exact SVD.  max_steps bounds the copy; *steps
    receives the number of steps available. */
 int smps_last_factor_log(const smps_ctx *ctx, int max_steps, int *kinds, int *steps);
+/* Per step of the last single-problem apply: the number of one-sided Jacobi
+   sweeps that applied a rotation in its exact factorization (0 for randomized
+   steps and for factorizations too large for the LDS-resident kernel).  Same
+   copy contract as smps_last_log. */
+int smps_last_jacobi_log(const smps_ctx *ctx, int max_steps, int *sweeps, int *steps);
 
 /* Compression of a linear combination (Sec. 2.4.1, Eq. mps-sum-opt):
    *out ~ sum_l w[l] U[l] v[l], the minimiser over MPS of bond <= max_bond of

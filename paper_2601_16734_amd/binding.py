@@ -35,7 +35,7 @@ EXPORTS = [
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
-    "smps_autotune_entries", "smps_dmrg",
+    "smps_autotune_entries", "smps_dmrg", "smps_last_jacobi_log",
 ]
 
 
@@ -113,6 +113,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_autotune_load": (c_int, [vp, ctypes.c_char_p]),
         "smps_autotune_clear": (c_int, [vp]),
         "smps_autotune_entries": (c_int, [vp, ip]),
+        "smps_last_jacobi_log": (c_int, [vp, c_int, ip, ip]),
         "smps_dmrg": (c_int, [vp, vp, vp, POINTER(Strategy), c_int, POINTER(vp), dp]),
         "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
                                        POINTER(c_float), c_int]),
@@ -376,6 +377,14 @@ class Context:
                                            ranks.ctypes.data_as(POINTER(c_int)),
                                            spec.ctypes.data_as(POINTER(c_double)), byref(n)))
         return deltas, ranks, spec
+
+    def last_jacobi_log(self) -> list:
+        """Rotating Jacobi sweeps of each step's exact factorization in the last apply."""
+        n = c_int()
+        self._check(self.lib.smps_last_jacobi_log(self.h, 0, None, byref(n)))
+        out = (c_int * max(1, n.value))()
+        self._check(self.lib.smps_last_jacobi_log(self.h, n.value, out, byref(n)))
+        return list(out)[:n.value]
 
     def last_factor_log(self) -> np.ndarray:
         n = c_int()

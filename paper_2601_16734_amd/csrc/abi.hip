@@ -642,6 +642,15 @@ int smps_autotune_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const
     return run_autotune(c, U, v, *st, reps, tuned);
 }
 
+int smps_last_jacobi_log(const smps_ctx* c, int max_steps, int* sweeps, int* steps) {
+    if (!c) return SMPS_EINVAL;
+    const int n = (int)c->log_sweeps.size();
+    if (steps) *steps = n;
+    const int m = std::min(n, std::max(0, max_steps));
+    if (sweeps) std::memcpy(sweeps, c->log_sweeps.data(), sizeof(int) * m);
+    return SMPS_OK;
+}
+
 int smps_last_factor_log(const smps_ctx* c, int max_steps, int* kinds, int* steps) {
     if (!c) return SMPS_EINVAL;
     const int n = (int)c->log_fact.size();

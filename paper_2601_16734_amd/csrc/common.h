@@ -98,6 +98,10 @@ struct JacobiDesc {
                          // s_j^2, so s_j = sqrt(row norm) and Q rows are divided by s_j^2
     const double* total_ext;  // nullable: exact total weight ||B||_F^2; the weight that the
                               // computed s_j miss is then counted in every tail
+    int accumulate;      // LDS kernel only: rotate an nvec x nvec matrix J (the identity at the
+                         // start) with the vectors; Q then receives the rows of J of the kept
+                         // values (the singular vectors on the nvec side, r x nvec) and basis,
+                         // when given, the whole J (nvec x nvec)
 };
 
 }  // namespace smps
@@ -124,10 +128,12 @@ size_t jacobi_work_doubles(int nvec_cap, int len_cap);
 hipError_t jacobi_init(int device);
 int jacobi_lds_limit();
 int jacobi_lds_class(int len_cap);
-size_t jacobi_lds_bytes(int nvec_cap, int len_cap);
+size_t jacobi_lds_bytes(int nvec_cap, int len_cap, bool accumulate = false);
 void jacobi_panel_params(int nvec_cap, int len_cap, int* bs, int* nblk);
 size_t jacobi_panel_bytes(int len_cap, int bs);
-hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s);
+// every descriptor of one launch has the same `accumulate` setting (acc)
+hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s,
+                                     bool acc = false);
 hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk, int max_rows,
                                        int len_cap, size_t shm, int sweeps, hipStream_t s);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
@@ -159,7 +165,7 @@ struct NormDesc {
     int* status;
 };
 hipError_t launch_norm_check_batched(const NormDesc* arr, int count, hipStream_t s);
-bool jacobi_fits_lds(int nvec_cap, int len_cap);
+bool jacobi_fits_lds(int nvec_cap, int len_cap, bool accumulate = false);
 hipError_t launch_copy(const double* src, double* dst, const int* dims, DimExpr a, DimExpr b, int cap,
                        hipStream_t s);
 hipError_t launch_fill(double* dst, double value, size_t n, hipStream_t s);

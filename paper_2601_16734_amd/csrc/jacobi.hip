@@ -152,9 +152,21 @@ __device__ __forceinline__ int pow2_ceil(int x) {
 //   visiting row goes through LDS, half the traffic of moving both rows.
 // * round-robin tournament (otherwise).
 // Returns (block-uniform) the number of sweeps that applied a rotation.
-template <int E, int G = 16>
+// Jw (nullable): an nv x nj matrix (row stride nj) receiving every rotation
+// applied to the vectors, so that it accumulates the product of the rotations.
+__device__ __forceinline__ void rotate_acc(double* Jw, int nj, int p, int q, int gl, int G, double cs, double sn) {
+    double* jp = Jw + (size_t)p * nj;
+    double* jq = Jw + (size_t)q * nj;
+    for (int i = gl; i < nj; i += G) {
+        const double a = jp[i], b = jq[i];
+        jp[i] = cs * a - sn * b;
+        jq[i] = sn * a + cs * b;
+    }
+}
+
+template <int E, int G = 16, bool ACC = false>
 __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double floor2,
-                             int true_len, int max_sweeps = JAC_MAX_SWEEPS) {
+                             int true_len, int max_sweeps = JAC_MAX_SWEEPS, double* Jw = nullptr, int nj = 0) {
     static_assert(G == 4 || G == 8 || G == 16, "group width");
     static_assert(E > 0 || G == 16, "generic path uses 16-lane groups");
     const int tid = threadIdx.x;
@@ -222,6 +234,7 @@ __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, in
                                         x[e] = cs * xe - sn * y[e];
                                         wq[gl + G * e] = sn * xe + cs * y[e];
                                     }
+                                    if constexpr (ACC) rotate_acc(Jw, nj, home, q, gl, G, cs, sn);
                                     a = fmax(a - t * c, 0.0);
                                     if (gl == 0) {
                                         nrm[q] = b + t * c;
@@ -294,6 +307,7 @@ __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, in
                             wq[i] = sn * xv + cs * yv;
                         }
                     }
+                    if constexpr (ACC) rotate_acc(Jw, nj, p, q, gl, G, cs, sn);
                     if (gl == 0) {
                         nrm[p] = fmax(a - t * c, 0.0);
                         nrm[q] = b + t * c;
@@ -424,7 +438,19 @@ __device__ int jacobi_select(const double* W, int nv, int len, int ld, double* s
 // Kept rows: Q[i] = W[perm[i]] / s_i (a zero vector only occurs when the
 // whole matrix is zero and one row is kept: it becomes the first unit vector).
 __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, const double* sig_sorted,
-                                  const int* perm, int r, double* Q, double* basis, int gram) {
+                                  const int* perm, int r, double* Q, double* basis, int gram,
+                                  const double* Jw = nullptr) {
+    if (Jw) {
+        // accumulated rotations: row perm[i] of J is the nvec-side singular
+        // vector of the i-th value (orthonormal also for zero values)
+        for (size_t e = threadIdx.x; e < (size_t)r * nv; e += blockDim.x) {
+            const int i = (int)(e / nv), l = (int)(e % nv);
+            Q[e] = Jw[(size_t)perm[i] * nv + l];
+        }
+        if (basis)
+            for (size_t e = threadIdx.x; e < (size_t)nv * nv; e += blockDim.x) basis[e] = Jw[e];
+        return;
+    }
     for (size_t e = threadIdx.x; e < (size_t)r * len; e += blockDim.x) {
         const int i = (int)(e / len), l = (int)(e % len);
         const double s = gram ? sig_sorted[i] * sig_sorted[i] : sig_sorted[i];
@@ -440,7 +466,7 @@ __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, cons
     }
 }
 
-template <int E>
+template <int E, bool ACC>
 __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d0, const JacobiDesc* arr) {
     constexpr int LDS_NT = lds_threads(E);
     extern __shared__ double sm[];
@@ -452,10 +478,13 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     const int ld = E > 0 ? 16 * E : len;
     const int tid = threadIdx.x;
     double* W = sm;
-    double* sig_raw = sm + (size_t)nv * ld;
+    double* Jw = ACC ? sm + (size_t)nv * ld : nullptr;  // nv x nv, starts as the identity
+    double* sig_raw = sm + (size_t)nv * ld + (ACC ? (size_t)nv * nv : 0);
     double* sig_sorted = sig_raw + nv;
     int* perm = (int*)(sig_sorted + nv);
     if (tid == 0) s_bad = 0;
+    if (Jw)
+        for (int e = tid; e < nv * nv; e += LDS_NT) Jw[e] = (e / nv == e % nv) ? 1.0 : 0.0;
     __syncthreads();
     int bad = 0;
     for (int e = tid; e < nv * ld; e += LDS_NT) {
@@ -492,11 +521,12 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
         }
         __syncthreads();
     }
-    const int nsw = jacobi_orth_t<E, 16>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag,
-                                      zero_floor2(s_total2, nv, len, d.floor_eps), len);
+    const int nsw = jacobi_orth_t<E, 16, ACC>(W, nv, E > 0 ? ld : len, ld, sig_raw, &s_flag,
+                                           zero_floor2(s_total2, nv, len, d.floor_eps), len, JAC_MAX_SWEEPS, Jw,
+                                           nv);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
-    jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram);
+    jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram, Jw);
 }
 
 // One round of the blocked path: workgroup i takes the block pair of
@@ -705,9 +735,12 @@ hipError_t jacobi_init(int device) {
     lim = lim < LDS_BYTES ? lim : LDS_BYTES;
     // the dynamic part may use what the kernels' static LDS leaves free
     size_t stat = 0;
-    const void* kernels[] = {(const void*)jacobi_lds_kernel<0>, (const void*)jacobi_lds_kernel<1>,
-                             (const void*)jacobi_lds_kernel<2>, (const void*)jacobi_lds_kernel<4>,
-                             (const void*)jacobi_lds_kernel<8>, (const void*)jacobi_lds_kernel<16>,
+    const void* kernels[] = {(const void*)jacobi_lds_kernel<0, false>, (const void*)jacobi_lds_kernel<1, false>,
+                             (const void*)jacobi_lds_kernel<2, false>, (const void*)jacobi_lds_kernel<4, false>,
+                             (const void*)jacobi_lds_kernel<8, false>, (const void*)jacobi_lds_kernel<16, false>,
+                             (const void*)jacobi_lds_kernel<0, true>,  (const void*)jacobi_lds_kernel<1, true>,
+                             (const void*)jacobi_lds_kernel<2, true>,  (const void*)jacobi_lds_kernel<4, true>,
+                             (const void*)jacobi_lds_kernel<8, true>,  (const void*)jacobi_lds_kernel<16, true>,
                              (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
                              (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
                              (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>};
@@ -729,18 +762,19 @@ hipError_t jacobi_init(int device) {
 
 int jacobi_lds_limit() { return g_lds_bytes; }
 
-static size_t lds_need(int nvec, int len) {
+static size_t lds_need(int nvec, int len, bool acc = false) {
     const int e = elems_for(len);
     const size_t ld = e > 0 ? 16 * (size_t)e : (size_t)len;
-    return sizeof(double) * ((size_t)nvec * ld + 2 * (size_t)nvec) + sizeof(int) * (size_t)nvec + 64;
+    return sizeof(double) * ((size_t)nvec * ld + (acc ? (size_t)nvec * nvec : 0) + 2 * (size_t)nvec) +
+           sizeof(int) * (size_t)nvec + 64;
 }
 
-bool jacobi_fits_lds(int nvec_cap, int len_cap) {
-    return nvec_cap <= SEL_MAX && lds_need(nvec_cap, len_cap) <= (size_t)g_lds_bytes - 1024;
+bool jacobi_fits_lds(int nvec_cap, int len_cap, bool acc) {
+    return nvec_cap <= SEL_MAX && lds_need(nvec_cap, len_cap, acc) <= (size_t)g_lds_bytes - 1024;
 }
 
 int jacobi_lds_class(int len_cap) { return elems_for(len_cap); }
-size_t jacobi_lds_bytes(int nvec_cap, int len_cap) { return lds_need(nvec_cap, len_cap); }
+size_t jacobi_lds_bytes(int nvec_cap, int len_cap, bool acc) { return lds_need(nvec_cap, len_cap, acc); }
 
 // Rows per block of the batched blocked path and the LDS its workgroups need:
 // two blocks of rows of length 16 E (zero padded, register path) or len_cap.
@@ -763,16 +797,25 @@ void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) 
 
 size_t jacobi_work_doubles(int, int) { return 0; }
 
-static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
+template <bool ACC>
+static void launch_lds_t(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
     const dim3 g(count), b(lds_threads(E));
     switch (E) {
-        case 1: hipLaunchKernelGGL(jacobi_lds_kernel<1>, g, b, shm, s, d, arr); break;
-        case 2: hipLaunchKernelGGL(jacobi_lds_kernel<2>, g, b, shm, s, d, arr); break;
-        case 4: hipLaunchKernelGGL(jacobi_lds_kernel<4>, g, b, shm, s, d, arr); break;
-        case 8: hipLaunchKernelGGL(jacobi_lds_kernel<8>, g, b, shm, s, d, arr); break;
-        case 16: hipLaunchKernelGGL(jacobi_lds_kernel<16>, g, b, shm, s, d, arr); break;
-        default: hipLaunchKernelGGL(jacobi_lds_kernel<0>, g, b, shm, s, d, arr); break;
+        case 1: hipLaunchKernelGGL((jacobi_lds_kernel<1, ACC>), g, b, shm, s, d, arr); break;
+        case 2: hipLaunchKernelGGL((jacobi_lds_kernel<2, ACC>), g, b, shm, s, d, arr); break;
+        case 4: hipLaunchKernelGGL((jacobi_lds_kernel<4, ACC>), g, b, shm, s, d, arr); break;
+        case 8: hipLaunchKernelGGL((jacobi_lds_kernel<8, ACC>), g, b, shm, s, d, arr); break;
+        case 16: hipLaunchKernelGGL((jacobi_lds_kernel<16, ACC>), g, b, shm, s, d, arr); break;
+        default: hipLaunchKernelGGL((jacobi_lds_kernel<0, ACC>), g, b, shm, s, d, arr); break;
     }
+}
+
+static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s,
+                       bool acc) {
+    if (acc)
+        launch_lds_t<true>(d, arr, count, E, shm, s);
+    else
+        launch_lds_t<false>(d, arr, count, E, shm, s);
 }
 
 // One sweep of the global-memory path (flag reset + one launch per round) as
@@ -861,10 +904,12 @@ static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, di
 hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
     (void)work;
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
-    if (jacobi_fits_lds(nvec_cap, len_cap)) {
-        launch_lds(d, nullptr, 1, elems_for(len_cap), lds_need(nvec_cap, len_cap), s);
+    if (jacobi_fits_lds(nvec_cap, len_cap, d.accumulate != 0)) {
+        launch_lds(d, nullptr, 1, elems_for(len_cap), lds_need(nvec_cap, len_cap, d.accumulate != 0), s,
+                   d.accumulate != 0);
         return hipGetLastError();
     }
+    if (d.accumulate) return hipErrorInvalidValue;  // accumulation is an LDS-kernel feature
     if (nvec_cap > SEL_MAX) return hipErrorInvalidValue;
     if (len_cap > 64 * 32) return hipErrorInvalidValue;
     // global-memory path: one launch per round of the tournament; `flags` is
@@ -904,10 +949,10 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
 
 // ---- batched forms (descriptor arrays on the device) -----------------------
 
-hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
+hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s, bool acc) {
     if (count <= 0) return hipSuccess;
     JacobiDesc none{};
-    launch_lds(none, arr, count, E, shm, s);
+    launch_lds(none, arr, count, E, shm, s, acc);
     return hipGetLastError();
 }
 

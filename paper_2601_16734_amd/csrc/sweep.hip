@@ -634,7 +634,7 @@ struct Enq {
     // randomized: this bond was factorized before in this call and a
     // randomized method is requested.
     hipError_t factor(int k, int step, bool rotate, bool randomized, double* theta, DimExpr nvec, DimExpr len,
-                      int nvec_cap, int len_cap, double* dest, int mr) const {
+                      int nvec_cap, int len_cap, double* dest, int mr, bool acc = false) const {
         if (randomized && !rec) {
             hipError_t e = read_dims();
             if (e != hipSuccess) return e;
@@ -654,10 +654,24 @@ struct Enq {
             hipError_t e = gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, nvec, len, nvec, 0, 0, 0, nvec_cap,
                                 len_cap, P_F64);
             if (e != hipSuccess) return e;
+        } else {
+            ++cur_slot;  // the same slot numbering whether or not this step pre-rotates
         }
         JacobiDesc d = jac(X, dest, nvec, len, k + 1, mr, st.tol, st.trunc_mode, step);
         d.basis = at<double>(p.o_basis[k]);
+        d.accumulate = acc;
         return jacobi(d, nvec_cap, len_cap);
+    }
+
+    // One-sided Jacobi converges slowly on more vectors than their length (the
+    // surplus must be rotated to zero) and such a step leaves no full basis to
+    // warm-start from.  When the side a step needs is the longer one, the
+    // vectors are taken along the shorter side instead and the rotations are
+    // accumulated (the needed singular vectors are rows of the accumulated
+    // matrix); exact factorizations in the LDS kernel only.
+    bool use_acc(int need_side, int other_side) const {
+        return st.factorization == SMPS_FACT_SVD && need_side < other_side &&
+               jacobi_fits_lds(need_side, other_side, true);
     }
 
     int eval_host(DimExpr x) const { return x.idx < 0 ? x.mul : x.mul * hdims[x.idx]; }
@@ -758,19 +772,26 @@ struct Enq {
             for (int k = 0; k + 1 < L; ++k) {  // left to right
                 tag(3 + 2 * sw, k);
                 double* theta = at<double>(p.o_theta);
+                // the left singular vectors are needed: rows of theta^T, or (acc) the
+                // accumulated rotations of theta's rows when those are the shorter side
+                const bool acc = use_acc(c[k] * e[k], e[k + 1] * c[k + 2]);
                 // theta = sum_t w_t XL_t[k] XR_t[k+1] (one term: the plain product)
                 for (int t = 0; t < NT; ++t) {
                     CK(build_XL(k, t));
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
                     CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
-                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, 1, c[k] * e[k], e[k + 1] * c[k + 2], p.prec,
-                            wt(t), t ? 1.0 : 0.0));
+                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, acc ? 0 : 1, c[k] * e[k], e[k + 1] * c[k + 2],
+                            p.prec, wt(t), t ? 1.0 : 0.0));
                 }
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start (sw > 0): rotate by the right singular basis this bond
                 // produced in the previous right-to-left pass (identity when it was not full)
-                CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
-                          c[k] * e[k], at<double>(p.o_Q), mr));
+                if (acc)
+                    CK(factor(k, step, false, rs_lr, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
+                              e[k + 1] * c[k + 2], at<double>(p.o_Q), mr, true));
+                else
+                    CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]),
+                              e[k + 1] * c[k + 2], c[k] * e[k], at<double>(p.o_Q), mr));
                 // Lenv_t[k+1] = Q XL_t[k]
                 for (int t = 0; t < NT; ++t) {
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
@@ -784,17 +805,24 @@ struct Enq {
             for (int k = L - 2; k >= 0; --k) {  // right to left
                 tag(4 + 2 * sw, L - 2 - k);
                 double* theta = at<double>(p.o_theta);
+                // the right singular vectors are needed: rows of theta, or (acc) the
+                // accumulated rotations of theta^T's rows when those are the shorter side
+                const bool acc = use_acc(e[k + 1] * c[k + 2], c[k] * e[k]);
                 for (int t = 0; t < NT; ++t) {
                     CK(build_XR(k + 1, at(oR(t, k + 2)), at(otmp(t)), at(oXR(t, k + 1)), p.et, p.prec, t));
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
                     CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
-                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, 0, c[k] * e[k], e[k + 1] * c[k + 2], p.prec,
-                            wt(t), t ? 1.0 : 0.0));
+                            ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, acc ? 1 : 0, c[k] * e[k], e[k + 1] * c[k + 2],
+                            p.prec, wt(t), t ? 1.0 : 0.0));
                 }
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start from the left singular basis of this pass's left-to-right visit
-                CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
-                          e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
+                if (acc)
+                    CK(factor(k, step, false, rs, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
+                              c[k] * e[k], at<double>(p.o_psi[k + 1]), mr, true));
+                else
+                    CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
+                              e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
                 for (int t = 0; t < NT; ++t)
                     CK(env_R(k + 1, at(oXR(t, k + 1)), at(oR(t, k + 1)), p.et, p.prec, t));
                 ++step;
@@ -1082,6 +1110,7 @@ struct Launch {
     LeftMpoDesc ltypes{};
     RightMpoDesc rtypes{};
     bool panel = false;
+    bool acc = false;  // LDS Jacobi launch: rotations accumulated
     int max_pairs = 0, max_nblk = 0, max_rows = 0;
 };
 
@@ -1095,13 +1124,32 @@ struct BatchCache {
     std::vector<Plan> plans;
 };
 
+// What must agree for ops to share one launch: the kind, and the template
+// arguments their launch is compiled for (types, transposes, precision).
+static std::vector<int> launch_signature(const Op& op) {
+    switch (op.kind) {
+        case OP_GEMM:
+            return {op.kind, op.g.ta, op.g.tb, op.g.tc, op.g.a_type, op.g.b_type, op.g.c_type, op.prec};
+        case OP_LEFT: return {op.kind, op.l.x_type, op.l.y_type};
+        case OP_RIGHT: return {op.kind, op.r.x_type, op.r.y_type};
+        default: return {op.kind};
+    }
+}
+
 static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& da, std::vector<Launch>& out) {
-    // group equal tags (phase, step, slot) across problems, in sequence order
-    std::map<std::tuple<int, int, int>, std::vector<const Op*>> groups;
+    // group equal tags (phase, step, slot) across problems, in sequence order;
+    // within a tag, problems whose ops differ in kind or template arguments (a
+    // step can be shaped differently in chains of different lengths) get
+    // launches of their own -- problems are independent, so their order does
+    // not matter
+    std::map<std::tuple<int, int, int>, std::map<std::vector<int>, std::vector<const Op*>>> tags;
     for (const auto& seq : ops)
-        for (const Op& op : seq) groups[std::make_tuple(op.major, op.j, op.slot)].push_back(&op);
-    for (auto& kv : groups) {
-        const auto& g = kv.second;
+        for (const Op& op : seq) tags[std::make_tuple(op.major, op.j, op.slot)][launch_signature(op)].push_back(&op);
+    std::vector<const std::vector<const Op*>*> groups;
+    for (auto& t : tags)
+        for (auto& sg : t.second) groups.push_back(&sg.second);
+    for (const auto* gp : groups) {
+        const auto& g = *gp;
         const OpKind kind = g[0]->kind;
         Launch ln;
         ln.kind = kind;
@@ -1155,10 +1203,12 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                 pl.kind = OP_JAC;
                 pl.panel = true;
                 for (const Op* o : g) {
-                    if (jacobi_fits_lds(o->cap0, o->cap1)) {
-                        const int E = jacobi_lds_class(o->cap1);
-                        lds[E].push_back(o->jd);
-                        lds_shm[E] = std::max(lds_shm[E], jacobi_lds_bytes(o->cap0, o->cap1));
+                    const bool acc = o->jd.accumulate != 0;
+                    if (jacobi_fits_lds(o->cap0, o->cap1, acc)) {
+                        // class key: register class E and whether rotations are accumulated
+                        const int key = 2 * jacobi_lds_class(o->cap1) + (acc ? 1 : 0);
+                        lds[key].push_back(o->jd);
+                        lds_shm[key] = std::max(lds_shm[key], jacobi_lds_bytes(o->cap0, o->cap1, acc));
                     } else {
                         JacobiDesc d = o->jd;
                         jacobi_panel_params(o->cap0, o->cap1, &d.bs, &d.nblk);
@@ -1173,7 +1223,8 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                 for (auto& cls : lds) {
                     Launch l2;
                     l2.kind = OP_JAC;
-                    l2.E = cls.first;
+                    l2.E = cls.first / 2;
+                    l2.acc = (cls.first & 1) != 0;
                     l2.shm = lds_shm[cls.first];
                     l2.count = (int)cls.second.size();
                     l2.off = da.add(cls.second.data(), sizeof(JacobiDesc) * cls.second.size());
@@ -1249,7 +1300,7 @@ static hipError_t enqueue_launches(const std::vector<Launch>& ls, char* dev, hip
                     e = launch_jacobi_panel_batched((const JacobiDesc*)arr, l.count, l.max_pairs, l.max_nblk,
                                                     l.max_rows, l.cap1, l.shm, PANEL_SWEEPS_BATCHED, s);
                 else
-                    e = launch_jacobi_lds_batched((const JacobiDesc*)arr, l.count, l.E, l.shm, s);
+                    e = launch_jacobi_lds_batched((const JacobiDesc*)arr, l.count, l.E, l.shm, s, l.acc);
                 break;
             case OP_COPY: e = launch_copy_batched((const CopyDesc*)arr, l.count, l.cap0, s); break;
             case OP_INTCOPY: e = launch_copy_int_batched((const IntCopyDesc*)arr, l.count, s); break;

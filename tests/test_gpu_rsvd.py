@@ -57,18 +57,23 @@ def test_randomized_schedule_matches_oracle(ctx, fact):
     assert np.max(np.abs(deltas - np.array(ref.deltas))) <= 1e-10 * scale
 
 
-def test_fallback_when_rank_is_underpredicted_is_identical_to_exact(ctx):
+def test_fallback_when_rank_is_underpredicted_matches_exact(ctx):
     """Predicted rank 1 (sketch 17) on bonds of rank ~25: every randomized step
-    is rejected and replaced by the exact SVD, so the result is bit-identical."""
+    is rejected and replaced by the exact SVD.  The exact mode factorizes the
+    steps whose needed side is the shorter one with accumulated rotations (the
+    randomized modes keep one orientation), so the two agree to rounding, with
+    the same ranks and discarded weights."""
     mps, mpo = decaying_case(16, 64, (3.0, 6.0), 1)
     constant_predictor(ctx, 1.0)
-    got, info, kinds, _ = run(ctx, mps, mpo, 64, 1e-10, 2, B.FACT_RSVD_MLP)
-    ref, info0, kinds0, _ = run(ctx, mps, mpo, 64, 1e-10, 2, B.FACT_SVD)
+    got, info, kinds, (deltas, ranks, _) = run(ctx, mps, mpo, 64, 1e-10, 2, B.FACT_RSVD_MLP)
+    ref, info0, kinds0, (deltas0, ranks0, _) = run(ctx, mps, mpo, 64, 1e-10, 2, B.FACT_SVD)
     assert info["rsvd_accepted"] == 0 and info["rsvd_fallbacks"] >= 10
     assert all(k <= 0 for k in kinds) and all(k == 0 for k in kinds0)
-    for a, b in zip(got, ref):
-        np.testing.assert_array_equal(a, b)
-    assert info["norm"] == info0["norm"]
+    assert list(ranks) == list(ranks0)
+    assert [t.shape for t in got] == [t.shape for t in ref]
+    assert np.max(np.abs(np.asarray(deltas) - np.asarray(deltas0))) <= 1e-12 * info0["norm"] ** 2
+    assert rel_norm_err(info["norm"], info0["norm"]) <= 1e-12
+    assert cross_fidelity_loss(got, ref) <= 1e-12
 
 
 def test_rejections_match_oracle_with_random_operator(ctx):
