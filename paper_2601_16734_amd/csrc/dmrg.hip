@@ -161,8 +161,11 @@ struct Dmrg {
     double* host = nullptr;  // pinned staging of hc
     int* host_ints = nullptr;  // pinned staging of the factorization's rank and status
     static constexpr double BREAKDOWN = 1e-12;  // beta <= BREAKDOWN |alpha|: invariant subspace found
-    static constexpr double RESIDUAL = 1e-11;   // stop once beta_j |y_j| <= RESIDUAL |E|
-    int first_chunk = 8, chunk = 4;
+    // stop once beta_j |y_j| <= RESIDUAL |E|: the Ritz value is then within
+    // about (RESIDUAL |E|)^2 / gap of the local eigenvalue, far below the
+    // truncation error, and the next visit of the pair refines the vector
+    static constexpr double RESIDUAL = 1e-7;
+    static constexpr int CHUNK = 4;  // Lanczos iterations between read-backs of the coefficients
     std::vector<void*> allocs;
     double energy = 0.0;
     int status_seen = 0;  // factorization status that stopped the run
@@ -345,7 +348,7 @@ struct Dmrg {
         std::vector<double> y;
         bool done = false;
         while (!done) {
-            const int j1 = std::min(mmax, j + (j == 0 ? first_chunk : chunk));
+            const int j1 = std::min(mmax, j + CHUNK);
             for (; j < j1; ++j) {
                 const double* vj = V + (size_t)j * n;
                 e = matvec(k, vj, w);
