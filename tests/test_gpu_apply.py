@@ -176,3 +176,23 @@ def test_nonfinite_input_reports_numeric_error(ctx):
     with pytest.raises(B.SmpsError) as e:
         ctx.mpo_apply(U, v, B.strategy(4, 1e-10))
     assert e.value.code == B.ENUMERIC
+
+
+def test_edge_steps_with_accumulated_rotations_match_oracle_step_by_step(ctx):
+    """n=12 chi=32 D=4: the steps near both ends factorize the shorter side
+    with accumulated rotations.  Every step's kept rank and discarded weight
+    equal the oracle's, the result's sites are exact right isometries, and the
+    per-step Jacobi sweep log accounts for every sweep reported."""
+    w = synth.workload_random_mpo(rep=5, L=12, chi=32, D=4)
+    ref = om.apply_simplify(w.mpo, w.mps, 32, 1e-10, sweeps=2)
+    got, err, info, _ = run_gpu(ctx, w, sweeps=2, max_bond=32, tol=1e-10)
+    deltas, ranks, _ = ctx.last_log()
+    assert list(ranks) == list(ref.step_ranks)
+    scale = ref.norm ** 2
+    assert np.max(np.abs(np.asarray(deltas) - np.asarray(ref.deltas))) <= 1e-10 * scale
+    assert rel_norm_err(info["norm"], ref.norm) <= 1e-12
+    assert cross_fidelity_loss(got, ref.mps) <= 1e-12
+    assert max(isometry_residual_right(t) for t in got[1:]) <= 1e-13
+    sweeps = ctx.last_jacobi_log()
+    assert len(sweeps) == info["steps"] and sum(sweeps) == info["jacobi_sweeps"]
+    assert all(s >= 0 for s in sweeps)
