@@ -426,7 +426,9 @@ def main():
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": measured_traffic(os.path.join(ROOT, "profiles", "jacobi_lds_c2_traffic.txt"),
                                             os.path.join(ROOT, "paper_2601_16734_amd", "csrc", "jacobi.hip")),
-                "avg_launch_ms": fact_avg_ms, "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"]}
+                "avg_launch_ms": fact_avg_ms, "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"],
+                # context: a factorization is one workgroup, so it can use one of the 256 CUs
+                "one_cu_peak": FP64_VECTOR_PEAK_TFLOPS / 256, "one_cu_frac": achieved / (FP64_VECTOR_PEAK_TFLOPS / 256)}
 
     line = {
         "metric": METRIC,
