@@ -65,6 +65,73 @@ def svd_flops(m: int, n: int) -> float:
     return 4.0 * l * k * k + 8.0 * k ** 3
 
 
+def contraction_flops(c, cv, D, d: int, sweeps: int) -> float:
+    """Flops of the contractions one apply performs (every bond at its cap c,
+    v's bonds cv, MPO bonds D): per update one X tensor (the environment times
+    v's site, then times the MPO site), the two-site product theta and the
+    environment update; the X tensor of the other side is reused from the
+    previous pass."""
+    L = len(c) - 1
+    f = 0.0
+    for _ in range(sweeps):
+        for k in range(L - 1):  # left to right: X_L[k], theta, L[k+1]
+            f += 2.0 * c[k] * D[k] * cv[k] * d * cv[k + 1] + 2.0 * c[k] * cv[k + 1] * D[k] * d * d * D[k + 1]
+            f += 2.0 * c[k] * d * D[k + 1] * cv[k + 1] * d * c[k + 2]
+            f += 2.0 * c[k + 1] * c[k] * d * D[k + 1] * cv[k + 1]
+        for k in range(L - 2, -1, -1):  # right to left: X_R[k+1], theta, R[k+1]
+            f += 2.0 * c[k + 2] * D[k + 2] * cv[k + 2] * d * cv[k + 1]
+            f += 2.0 * c[k + 2] * cv[k + 1] * D[k + 2] * d * d * D[k + 1]
+            f += 2.0 * c[k] * d * D[k + 1] * cv[k + 1] * d * c[k + 2]
+            f += 2.0 * c[k + 1] * d * c[k + 2] * D[k + 1] * cv[k + 1]
+    return f
+
+
+# dense MFMA peaks (TFLOP/s) of the arithmetic each contraction precision runs on,
+# and how many MFMA products it issues per algorithmic product
+MFMA_PEAK = {"fp64": (78.6, 1), "fp32": (157.3, 1), "bf16x3": (2500.0, 3), "bf16": (2500.0, 1)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(fn, budget_s: float):
+    """Time fn() on all BLAS threads and on one thread, each for about half of
+    the budget (at least one call), and return (seconds per call, threads) of
+    the faster setting plus both measurements.  Small contractions often run
+    faster on one thread than on many."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        all_threads = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits, all_threads = None, os.cpu_count()
+
+    def run(limit):
+        t0 = time.perf_counter()
+        reps = 0
+        while True:
+            if limit is None or threadpool_limits is None:
+                fn()
+            else:
+                with threadpool_limits(limits=limit):
+                    fn()
+            reps += 1
+            if time.perf_counter() - t0 >= 0.5 * budget_s:
+                break
+        return (time.perf_counter() - t0) / reps, reps
+
+    many, reps_many = run(None)
+    one, reps_one = run(1)
+    best = (one, 1, reps_one) if one < many else (many, int(all_threads), reps_many)
+    return best, {"s_per_call_all_threads": many, "threads_all": int(all_threads), "s_per_call_1_thread": one}
+
+
 def measured_traffic(path: str, source: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source (None otherwise)."""
@@ -205,17 +272,16 @@ def dmrg_leg(args):
             r["exact_energy"] = ex
             r["rel_energy_error"] = (r["energy"] - ex) / abs(ex)
         L = 16
-        t = time.perf_counter()
-        _, _, en = od.dmrg(synth.tfim_mpo(L, 1.0, 1.0), synth.random_mps(np.random.default_rng(70), L, 2, 4),
-                           max_bond=256, tol=1e-12 / (L - 1), sweeps=2)
-        dt = time.perf_counter() - t
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
-        out["cpu_baseline"] = {"value": len(en) / dt, "unit": "site-updates/s", "cores": int(cores),
-                               "kind": "oracle", "sample": f"oracle DMRG, L={L}, 2 sweeps ({len(en)} updates)"}
+        Hn, gn = synth.tfim_mpo(L, 1.0, 1.0), synth.random_mps(np.random.default_rng(70), L, 2, 4)
+        n_up = 2 * 2 * (L - 1)
+        (dt, cores, reps), both = time_oracle(
+            lambda: od.dmrg(Hn, gn, max_bond=256, tol=1e-12 / (L - 1), sweeps=2), 8.0)
+        out["cpu_baseline"] = {"value": n_up / dt, "unit": "site-updates/s", "cores": int(cores),
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"oracle DMRG, L={L}, 2 sweeps ({n_up} updates), {reps} runs on the "
+                                         f"faster of all BLAS threads and one thread",
+                               "value_all_threads": n_up / both["s_per_call_all_threads"],
+                               "value_1_thread": n_up / both["s_per_call_1_thread"]}
     print(json.dumps(out))
     ctx.close()
 
@@ -290,19 +356,22 @@ def diffusion_leg(args):
         lap = synth.laplacian_mpo(n, dx=dx)
         lap[0] = nu * lap[0]
         from oracle import mps as om
-        y = om.simplify(synth.placement_mps(synth.gaussian_grid(n), n), 2 ** (n // 2), 1e-12 / (n - 1), 4).mps
-        k = 20
-        t = time.perf_counter()
-        for _ in range(k):
-            y = oe.rk4_step(lap, y, dx * dx / (20.0 * nu), 2 ** (n // 2), 1e-12 / (n - 1), sweeps=2)
-        sec = time.perf_counter() - t
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
+        y0 = om.simplify(synth.placement_mps(synth.gaussian_grid(n), n), 2 ** (n // 2), 1e-12 / (n - 1), 4).mps
+        k = 5
+        state = {"y": y0}
+
+        def oracle_steps():
+            for _ in range(k):
+                state["y"] = oe.rk4_step(lap, state["y"], dx * dx / (20.0 * nu), 2 ** (n // 2), 1e-12 / (n - 1),
+                                         sweeps=2)
+
+        (sec, cores, reps), both = time_oracle(oracle_steps, 8.0)
         out["cpu_baseline"] = {"value": k / sec, "unit": "RK4 steps/s", "cores": int(cores), "kind": "oracle",
-                               "sample": f"oracle RK4 step (2 sweeps per compression), n={n}, {k} steps"}
+                               "cpu_model": cpu_model(),
+                               "sample": f"oracle RK4 step (2 sweeps per compression), n={n}, {reps} x {k} steps "
+                                         f"on the faster of all BLAS threads and one thread",
+                               "value_all_threads": k / both["s_per_call_all_threads"],
+                               "value_1_thread": k / both["s_per_call_1_thread"]}
     print(json.dumps(out))
     ctx.close()
 
@@ -349,22 +418,15 @@ def main():
     ref = None
     if not args.no_cpu:
         from oracle import mps as om
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
-        t0 = time.perf_counter()
-        reps = 0
-        while True:
-            ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=w.sweeps)
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        dt = (time.perf_counter() - t0) / reps
+        ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=w.sweeps)
+        (dt, cores, reps), both = time_oracle(
+            lambda: om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=w.sweeps), args.cpu_seconds)
         cpu = {"value": site_updates / dt, "unit": "site-updates/s", "cores": int(cores), "kind": "oracle",
                "sample": f"{reps} full apply+compress runs of the same workload ({site_updates} site-updates "
-                         f"each, {dt:.2f} s per run, FP64 NumPy/SciPy)"}
+                         f"each, {dt:.2f} s per run, FP64 NumPy/SciPy) on the faster of all BLAS threads and "
+                         f"one thread", "cpu_model": cpu_model(),
+               "value_all_threads": site_updates / both["s_per_call_all_threads"],
+               "threads_all": both["threads_all"], "value_1_thread": site_updates / both["s_per_call_1_thread"]}
 
     # theta shapes along the sweep (bond dims reach the cap for this workload)
     caps = synth.bond_caps(L, 2, w.max_bond)
@@ -373,6 +435,8 @@ def main():
         for k in list(range(L - 1)) + list(range(L - 2, -1, -1)):
             flops_per_apply += svd_flops(2 * caps[k], 2 * caps[k + 2])
 
+    cflops = contraction_flops(caps, [1] + [t.shape[2] for t in w.mps], [1] + [t.shape[3] for t in w.mpo], 2,
+                               w.sweeps)
     results = {}
     stream = torch.cuda.current_stream()
     tuned = {}
@@ -386,20 +450,30 @@ def main():
         torch.cuda.synchronize()
         ctx.set_profiling(True)
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         outs = []
         start.record(stream)
-        for _ in range(args.steps):
+        for i in range(args.steps):
             out, _ = ctx.mpo_apply(U, v, st)
             outs.append(out)
+            marks[i].record(stream)
         stop.record(stream)
         torch.cuda.synchronize()
         ms = start.elapsed_time(stop) / args.steps
+        per = np.array([start.elapsed_time(marks[0])] +
+                       [marks[i - 1].elapsed_time(marks[i]) for i in range(1, args.steps)])
         fact_ms, fact_n = ctx.kernel_time(0)
         ctx.set_profiling(False)
         info = ctx.last_info()
+        contr_ms = max(1e-9, ms - fact_ms / args.steps)
+        peak, issue = MFMA_PEAK.get(prec, (78.6, 1))
         rec = {"ms_per_step": ms, "site_updates_per_s": site_updates / (ms / 1e3),
+               "step_ms_median": float(np.median(per)),
+               "step_ms_iqr": float(np.percentile(per, 75) - np.percentile(per, 25)),
                "factorization_ms_per_step": fact_ms / args.steps,
-               "factorization_launches_per_step": fact_n / args.steps, "norm": info["norm"]}
+               "factorization_launches_per_step": fact_n / args.steps, "norm": info["norm"],
+               "contraction_tflops": cflops / (contr_ms * 1e-3) / 1e12,
+               "contraction_mfma_frac": issue * cflops / (contr_ms * 1e-3) / 1e12 / peak}
         if ref is not None:
             from oracle import mps as om
             got = outs[-1].read()
