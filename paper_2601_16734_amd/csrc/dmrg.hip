@@ -6,8 +6,10 @@
 // H_k a = L[k] W_k W_{k+1} R[k+2] a (three-layer environments of <psi|H|psi>).
 // It is solved matrix-free by Lanczos: every product with H_k is two GEMMs
 // and two MPO-site contractions on the device; the Krylov basis stays on the
-// device and is re-orthogonalised by GEMMs; only the small tridiagonal
-// eigenproblem (at most a few tens of rows) is solved on the host.  The pair
+// device and every new vector is re-orthogonalised against it twice (one
+// workgroup per basis vector for the projections, one pass for the update);
+// only the small tridiagonal eigenproblem (at most a few tens of rows) is
+// solved on the host.  The pair
 // is then split by the one-sided Jacobi SVD with the strategy's truncation and
 // the environment on the side the centre leaves is extended.  Bond dimensions
 // are read back after every split, so every launch here has host-known sizes.
