@@ -156,6 +156,13 @@ struct Dmrg {
     int L, m;
     std::vector<int> d, D, chi, cap;
     std::vector<double*> psi, Lenv, Renv;
+    // per bond: the singular basis the last split there left (len x len of that
+    // factorization, the identity when its vectors did not span), and that len
+    // (0: none yet).  The next split at the bond pre-rotates its vectors by it
+    // when their count equals that len (the opposite visit's orientation).
+    std::vector<double*> basis;
+    std::vector<int> basis_dim;
+    double* jx2 = nullptr;
     double *theta = nullptr, *V = nullptr, *w = nullptr, *x1 = nullptr, *x2 = nullptr, *x3 = nullptr;
     double *jx = nullptr, *Q = nullptr, *sigma = nullptr, *scal = nullptr, *fro2 = nullptr, *tmp = nullptr;
     int* ints = nullptr;  // [rank, status, flag, perm...]
@@ -261,8 +268,17 @@ struct Dmrg {
 
     // Rows of X (nv x ln) orthogonalised; the first r rows of Q are the kept
     // right singular vectors.  tol < 0: keep every nonzero value (no truncation).
-    hipError_t svd_rows(double* X, int nv, int ln, int max_rank, double tol, int* r_out) {
+    hipError_t svd_rows(double* X, int nv, int ln, int max_rank, double tol, int* r_out, int bond = -1) {
+        if (bond >= 0 && basis_dim[bond] == nv) {  // warm start
+            hipError_t e = mm(basis[bond], X, jx2, nv, ln, nv, 0, 0);
+            if (e != hipSuccess) return e;
+            X = jx2;
+        }
         JacobiDesc jd{};
+        if (bond >= 0) {
+            jd.basis = basis[bond];
+            basis_dim[bond] = ln;
+        }
         jd.X = X;
         jd.Q = Q;
         jd.sigma = sigma;
@@ -419,7 +435,7 @@ struct Dmrg {
             // left isometry: rows of theta^T are the columns of theta
             e = transpose(theta, jx, a * sd, td * cc);
             if (e != hipSuccess) return e;
-            e = svd_rows(jx, td * cc, a * sd, mr, st.tol, &r);
+            e = svd_rows(jx, td * cc, a * sd, mr, st.tol, &r, k);
             if (e != hipSuccess) return e;
             e = transpose(Q, psi[k], r, a * sd);  // psi_k = U (a s x r)
             if (e != hipSuccess) return e;
@@ -430,7 +446,7 @@ struct Dmrg {
         }
         e = hipMemcpyAsync(jx, theta, sizeof(double) * (size_t)a * sd * td * cc, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
-        e = svd_rows(jx, a * sd, td * cc, mr, st.tol, &r);
+        e = svd_rows(jx, a * sd, td * cc, mr, st.tol, &r, k);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(psi[k + 1], Q, sizeof(double) * (size_t)r * td * cc, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
@@ -485,10 +501,17 @@ struct Dmrg {
         }
         ok = ok && (theta = alloc<double>(nth)) && (V = alloc<double>(nth * (size_t)(m + 1))) &&
              (w = alloc<double>(nth)) && (x1 = alloc<double>(nx)) && (x2 = alloc<double>(nx)) &&
-             (x3 = alloc<double>(nx)) && (jx = alloc<double>(nth)) && (Q = alloc<double>(nth)) &&
+             (x3 = alloc<double>(nx)) && (jx = alloc<double>(nth)) && (jx2 = alloc<double>(nth)) &&
+             (Q = alloc<double>(nth)) &&
              (sigma = alloc<double>(nvmax)) && (scal = alloc<double>(1)) && (fro2 = alloc<double>(1)) &&
              (tmp = alloc<double>(std::max<size_t>(nth, (size_t)m + 1))) && (ints = alloc<int>(3 + (size_t)nvmax)) &&
              (hc = alloc<double>(2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)));
+        basis.assign(std::max(0, L - 1), nullptr);
+        basis_dim.assign(std::max(0, L - 1), 0);
+        for (int k = 0; k + 1 < L; ++k) {
+            const size_t nb = std::max((size_t)cap[k] * d[k], (size_t)d[k + 1] * cap[k + 2]);
+            ok = ok && (basis[k] = alloc<double>(nb * nb));
+        }
         if (!ok) return fail(c, SMPS_ENOMEM, "DMRG workspace allocation failed");
         {
             const size_t hb = (2 * (size_t)(m + 1) * (m + 1) + 2 * (size_t)(m + 1)) * sizeof(double);
