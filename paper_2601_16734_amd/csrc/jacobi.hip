@@ -468,7 +468,7 @@ __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, cons
 
 template <int E, bool ACC>
 __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d0, const JacobiDesc* arr) {
-    constexpr int LDS_NT = lds_threads(E);
+    const int LDS_NT = blockDim.x;  // at most lds_threads(E); fewer for few vectors
     extern __shared__ double sm[];
     const JacobiDesc d = arr ? arr[blockIdx.x] : d0;  // batched: one factorization per workgroup
     __shared__ int s_flag, s_bad;
@@ -798,8 +798,9 @@ void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) 
 size_t jacobi_work_doubles(int, int) { return 0; }
 
 template <bool ACC>
-static void launch_lds_t(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s) {
-    const dim3 g(count), b(lds_threads(E));
+static void launch_lds_t(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s,
+                         int threads) {
+    const dim3 g(count), b(threads);
     switch (E) {
         case 1: hipLaunchKernelGGL((jacobi_lds_kernel<1, ACC>), g, b, shm, s, d, arr); break;
         case 2: hipLaunchKernelGGL((jacobi_lds_kernel<2, ACC>), g, b, shm, s, d, arr); break;
@@ -810,12 +811,24 @@ static void launch_lds_t(const JacobiDesc& d, const JacobiDesc* arr, int count, 
     }
 }
 
+// nvec_cap > 0: a workgroup just large enough for the pairs of nvec_cap
+// vectors (16 lanes per pair, the pair count rounded up to a power of two as
+// the home/away ordering needs, at least one wave); 0: the class maximum.
+static int lds_launch_threads(int E, int nvec_cap) {
+    const int full = lds_threads(E);
+    if (nvec_cap <= 0) return full;
+    int p2 = 1;
+    while (p2 < (nvec_cap + 1) / 2) p2 <<= 1;
+    return std::max(64, std::min(full, 16 * p2));
+}
+
 static void launch_lds(const JacobiDesc& d, const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s,
-                       bool acc) {
+                       bool acc, int nvec_cap = 0) {
+    const int threads = lds_launch_threads(E, nvec_cap);
     if (acc)
-        launch_lds_t<true>(d, arr, count, E, shm, s);
+        launch_lds_t<true>(d, arr, count, E, shm, s, threads);
     else
-        launch_lds_t<false>(d, arr, count, E, shm, s);
+        launch_lds_t<false>(d, arr, count, E, shm, s, threads);
 }
 
 // One sweep of the global-memory path (flag reset + one launch per round) as
@@ -906,7 +919,7 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
     if (jacobi_fits_lds(nvec_cap, len_cap, d.accumulate != 0)) {
         launch_lds(d, nullptr, 1, elems_for(len_cap), lds_need(nvec_cap, len_cap, d.accumulate != 0), s,
-                   d.accumulate != 0);
+                   d.accumulate != 0, nvec_cap);
         return hipGetLastError();
     }
     if (d.accumulate) return hipErrorInvalidValue;  // accumulation is an LDS-kernel feature
