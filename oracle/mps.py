@@ -414,7 +414,7 @@ def unfolding_tail_bound(vec, dims, max_bond: int) -> float:
     cut, the weight beyond the first max_bond singular values of that
     unfolding (Eckart-Young); return the largest over cuts."""
     best = 0.0
-    v = np.asarray(vec, dtype=np.float64)
+    v = np.asarray(vec)  # real or complex
     left = 1
     for k in range(len(dims) - 1):
         left *= dims[k]

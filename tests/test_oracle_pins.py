@@ -567,3 +567,61 @@ def test_oracle_rk4_amplifies_a_laplacian_eigenvector_by_the_rk4_factor():
     assert np.max(np.abs(dense.mps_to_dense(y) - want)) <= 1e-12 * np.max(np.abs(want))
     got_dense = oe.dense_rk4(dense.mpo_to_dense(H), dense.mps_to_dense(y0), dt, 2)
     assert np.max(np.abs(got_dense - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+# ---- complex arithmetic (apply + compression of complex MPS / MPO) -------------
+
+def _zrand_mps(rng, L, d, chi):
+    return [a + 1j * b for a, b in zip(synth.random_mps(rng, L, d, chi), synth.random_mps(rng, L, d, chi))]
+
+
+def _zrand_mpo(rng, L, d, D):
+    return [a + 1j * b for a, b in zip(synth.random_mpo(rng, L, d, D), synth.random_mpo(rng, L, d, D))]
+
+
+def test_complex_apply_without_truncation_is_the_dense_product():
+    from oracle import zmps
+    rng = np.random.default_rng(90)
+    v, U = _zrand_mps(rng, 6, 2, 3), _zrand_mpo(rng, 6, 2, 2)
+    psi, nrm, _ = zmps.apply_simplify(U, v, max_bond=64, tol=0.0, sweeps=2)
+    want = dense.mpo_to_dense(U) @ dense.mps_to_dense(v)
+    got = dense.mps_to_dense(psi)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert abs(nrm - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+    # the transfer-matrix scalar product against the dense one
+    assert abs(zmps.scprod(psi, v) - np.vdot(got, dense.mps_to_dense(v))) <= 1e-12 * abs(np.vdot(got, got)) ** 0.5 * \
+        np.linalg.norm(dense.mps_to_dense(v))
+
+
+def test_complex_oracle_reduces_to_the_real_one_on_real_input():
+    from oracle import zmps
+    rng = np.random.default_rng(91)
+    v, U = synth.random_mps(rng, 8, 2, 6), synth.random_mpo(rng, 8, 2, 3)
+    psi, nrm, deltas = zmps.apply_simplify(U, v, max_bond=5, tol=1e-10, sweeps=2)
+    ref = om.apply_simplify(U, v, max_bond=5, tol=1e-10, sweeps=2)
+    assert abs(nrm - ref.norm) <= 1e-12 * ref.norm
+    assert np.max(np.abs(np.asarray(deltas) - np.asarray(ref.deltas))) <= 1e-12 * ref.norm ** 2
+    ov = abs(np.vdot(dense.mps_to_dense(psi), dense.mps_to_dense(ref.mps)))
+    assert abs(ov / (nrm * ref.norm) - 1.0) <= 1e-12
+
+
+def test_complex_compression_is_phase_covariant_and_optimal_when_truncated():
+    # U -> e^{i phi} U multiplies the compressed result by e^{i phi}; and the
+    # compressed state never beats the best rank-limited approximation
+    # (distance >= the Eckart-Young bound of the dense product)
+    from oracle import zmps
+    rng = np.random.default_rng(92)
+    v, U = _zrand_mps(rng, 8, 2, 4), _zrand_mpo(rng, 8, 2, 3)
+    psi, nrm, _ = zmps.apply_simplify(U, v, max_bond=6, tol=0.0, sweeps=3)
+    ph = np.exp(0.7j)
+    Up = [U[0] * ph] + U[1:]
+    psi2, nrm2, _ = zmps.apply_simplify(Up, v, max_bond=6, tol=0.0, sweeps=3)
+    a, b = dense.mps_to_dense(psi), dense.mps_to_dense(psi2)
+    assert abs(nrm2 - nrm) <= 1e-12 * nrm
+    assert np.max(np.abs(b - ph * a)) <= 1e-10 * np.max(np.abs(a))
+    w = dense.mpo_to_dense(U) @ dense.mps_to_dense(v)
+    dist2 = np.linalg.norm(w - a) ** 2
+    bound = om.unfolding_tail_bound(w, [2] * 8, 6)
+    assert dist2 >= bound * (1 - 1e-9)
+    # the variational result is the projection: |<psi, Uv>| = |psi|^2
+    assert abs(abs(np.vdot(a, w)) - nrm ** 2) <= 1e-10 * nrm ** 2
