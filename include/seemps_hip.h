@@ -222,6 +222,38 @@ int smps_mpo_list_apply(smps_ctx *ctx, int n, const smps_mpo *const *U, const sm
 int smps_mpo_simplify(smps_ctx *ctx, const smps_mpo *U, const smps_strategy *strategy, smps_mpo **out,
                       double *trunc_err);
 
+/* Complex arithmetic (complex MPS / MPO; Sec. 2.1-2.4 with complex tensors).
+ * Handles of complex states and operators are separate types.  Tensors are
+ * complex128 in C order, the real and imaginary parts interleaved (re, im):
+ * a site of `count` complex entries is 2 * count doubles; index orders are the
+ * real path's ((chi_l, d, chi_r) and (D_l, d_out, d_in, D_r)).
+ *   smps_zmps_create / smps_zmpo_create: copy host tensors to the device;
+ *       smps_zmps_read copies one site back (count = complex entries).
+ *   smps_zmpo_apply: psi ~ U v, compressed by the two-site variational sweep
+ *       with the bra conjugated in the environments and a complex one-sided
+ *       Jacobi SVD per split; strategy as for smps_mpo_apply but FP64 and the
+ *       exact factorization only (SMPS_EUNSUPPORTED otherwise), square
+ *       operator sites matching the state; two-site tensors must fit the
+ *       factorization's LDS (about 9000 complex entries, SMPS_EUNSUPPORTED
+ *       beyond); *out has its centre at site 0 and is not normalised;
+ *       *trunc_err (nullable) receives the error bound; smps_last_info reports
+ *       norm, steps and discarded weight.
+ *   smps_zscprod: <a, b> = sum conj(a) b (Sec. 2.4.4), real and imaginary
+ *       parts written to *re, *im. */
+typedef struct smps_zmps smps_zmps;
+typedef struct smps_zmpo smps_zmpo;
+int smps_zmps_create(smps_ctx *ctx, int L, const int *phys, const int *bonds, const double *const *tensors,
+                     smps_zmps **out);
+int smps_zmps_destroy(smps_zmps *mps);
+int smps_zmps_shape(const smps_zmps *mps, int *L, int *phys, int *bonds);
+int smps_zmps_read(smps_ctx *ctx, const smps_zmps *mps, int site, double *host_out, size_t count);
+int smps_zmpo_create(smps_ctx *ctx, int L, const int *pout, const int *pin, const int *bonds,
+                     const double *const *tensors, smps_zmpo **out);
+int smps_zmpo_destroy(smps_zmpo *mpo);
+int smps_zmpo_apply(smps_ctx *ctx, const smps_zmpo *U, const smps_zmps *v, const smps_strategy *strategy,
+                    smps_zmps **out, double *trunc_err);
+int smps_zscprod(smps_ctx *ctx, const smps_zmps *a, const smps_zmps *b, double *re, double *im);
+
 /* Ground-state search by two-site DMRG (Sec. 3.1.1).  H: a real symmetric
  * operator with pout == pin == the guess's physical dimensions.  guess: any
  * nonzero MPS of that shape (not modified; it is right-canonicalised and

@@ -36,6 +36,8 @@ EXPORTS = [
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
     "smps_autotune_entries", "smps_dmrg", "smps_last_jacobi_log",
+    "smps_zmps_create", "smps_zmps_destroy", "smps_zmps_shape", "smps_zmps_read", "smps_zmpo_create",
+    "smps_zmpo_destroy", "smps_zmpo_apply", "smps_zscprod",
 ]
 
 
@@ -114,6 +116,14 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_autotune_clear": (c_int, [vp]),
         "smps_autotune_entries": (c_int, [vp, ip]),
         "smps_last_jacobi_log": (c_int, [vp, c_int, ip, ip]),
+        "smps_zmps_create": (c_int, [vp, c_int, ip, ip, POINTER(dp), POINTER(vp)]),
+        "smps_zmps_destroy": (c_int, [vp]),
+        "smps_zmps_shape": (c_int, [vp, ip, ip, ip]),
+        "smps_zmps_read": (c_int, [vp, vp, c_int, dp, ctypes.c_size_t]),
+        "smps_zmpo_create": (c_int, [vp, c_int, ip, ip, ip, POINTER(dp), POINTER(vp)]),
+        "smps_zmpo_destroy": (c_int, [vp]),
+        "smps_zmpo_apply": (c_int, [vp, vp, vp, POINTER(Strategy), POINTER(vp), dp]),
+        "smps_zscprod": (c_int, [vp, vp, vp, dp, dp]),
         "smps_dmrg": (c_int, [vp, vp, vp, POINTER(Strategy), c_int, POINTER(vp), dp]),
         "smps_rank_mlp_grad": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), POINTER(c_float),
                                        POINTER(c_float), c_int]),
@@ -218,6 +228,64 @@ class MPO:
     def __del__(self):
         try:
             if self.h and self.ctx.h:
+                self.destroy()
+        except Exception:
+            pass
+
+
+class ZMPS:
+    """Handle of a device complex MPS (owned; freed on destroy / garbage collection)."""
+
+    def __init__(self, ctx: "Context", handle: c_void_p):
+        self.ctx = ctx
+        self.h = handle
+
+    def shape(self):
+        L = c_int()
+        self.ctx._check(self.ctx.lib.smps_zmps_shape(self.h, byref(L), None, None))
+        phys = (c_int * L.value)()
+        bonds = (c_int * (L.value + 1))()
+        self.ctx._check(self.ctx.lib.smps_zmps_shape(self.h, None, phys, bonds))
+        return list(phys), list(bonds)
+
+    def read(self) -> list[np.ndarray]:
+        phys, bonds = self.shape()
+        out = []
+        for k in range(len(phys)):
+            a = np.empty((bonds[k], phys[k], bonds[k + 1]), dtype=np.complex128)
+            self.ctx._check(self.ctx.lib.smps_zmps_read(self.ctx.h, self.h, k, a.ctypes.data_as(POINTER(c_double)),
+                                                        a.size))
+            out.append(a)
+        return out
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.smps_zmps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.ctx.h:
+                self.destroy()
+        except Exception:
+            pass
+
+
+class ZMPO:
+    """Handle of a device complex MPO."""
+
+    def __init__(self, ctx: "Context", handle: c_void_p):
+        self.ctx = ctx
+        self.h = handle
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.smps_zmpo_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            if self.ctx.h:
                 self.destroy()
         except Exception:
             pass
@@ -341,6 +409,41 @@ class Context:
         e = c_double()
         self._check(self.lib.smps_dmrg(self.h, H.h, guess.h, byref(st), int(krylov_dim), byref(out), byref(e)))
         return MPS(self, out), e.value
+
+    # ---- complex states and operators (interleaved complex128 on the host side)
+    def zmps_create(self, tensors) -> "ZMPS":
+        arrs = [np.ascontiguousarray(t, dtype=np.complex128) for t in tensors]
+        L = len(arrs)
+        phys = (c_int * L)(*[a.shape[1] for a in arrs])
+        bonds = (c_int * (L + 1))(*([arrs[0].shape[0]] + [a.shape[2] for a in arrs]))
+        dpt = POINTER(c_double)
+        ptrs = (dpt * L)(*[a.ctypes.data_as(dpt) for a in arrs])
+        out = c_void_p()
+        self._check(self.lib.smps_zmps_create(self.h, L, phys, bonds, ptrs, byref(out)))
+        return ZMPS(self, out)
+
+    def zmpo_create(self, tensors) -> "ZMPO":
+        arrs = [np.ascontiguousarray(t, dtype=np.complex128) for t in tensors]
+        L = len(arrs)
+        pout = (c_int * L)(*[a.shape[1] for a in arrs])
+        pin = (c_int * L)(*[a.shape[2] for a in arrs])
+        bonds = (c_int * (L + 1))(*([arrs[0].shape[0]] + [a.shape[3] for a in arrs]))
+        dpt = POINTER(c_double)
+        ptrs = (dpt * L)(*[a.ctypes.data_as(dpt) for a in arrs])
+        out = c_void_p()
+        self._check(self.lib.smps_zmpo_create(self.h, L, pout, pin, bonds, ptrs, byref(out)))
+        return ZMPO(self, out)
+
+    def zmpo_apply(self, U: "ZMPO", v: "ZMPS", st: Strategy):
+        out = c_void_p()
+        err = c_double()
+        self._check(self.lib.smps_zmpo_apply(self.h, U.h, v.h, byref(st), byref(out), byref(err)))
+        return ZMPS(self, out), err.value
+
+    def zscprod(self, a: "ZMPS", b: "ZMPS") -> complex:
+        re, im = c_double(), c_double()
+        self._check(self.lib.smps_zscprod(self.h, a.h, b.h, byref(re), byref(im)))
+        return complex(re.value, im.value)
 
     def mpo_apply_batched(self, Us, vs, st: Strategy):
         n = len(vs)
