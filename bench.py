@@ -51,6 +51,9 @@ def parse():
                     help="only measure the RK4 integration of the diffusion equation (Gaussian initial state on "
                          "2^N grid points, 1000 steps) and print its JSON line")
     ap.add_argument("--rk4-steps", type=int, default=1000)
+    ap.add_argument("--complex", action="store_true",
+                    help="only measure the complex apply + compression (random complex MPO D=4 on a random complex "
+                         "MPS n=20 chi=32, max bond 32, tol 1e-10, 4 sweeps) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -376,6 +379,63 @@ def diffusion_leg(args):
     ctx.close()
 
 
+def complex_leg(args):
+    """Complex FP64 apply + compression: entries of both tensors with real and
+    imaginary parts drawn like the real workloads'; inputs resident before
+    timing; the oracle (complex route F) checks the timed output and is timed
+    beside it on the faster of all BLAS threads and one thread."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    n, chi, D, sweeps = 20, 32, 4, 4
+    rng = np.random.default_rng(120)
+    v = [a + 1j * b for a, b in zip(synth.random_mps(rng, n, 2, chi), synth.random_mps(rng, n, 2, chi))]
+    U = [a + 1j * b for a, b in zip(synth.random_mpo(rng, n, 2, D), synth.random_mpo(rng, n, 2, D))]
+    zv, zU = ctx.zmps_create(v), ctx.zmpo_create(U)
+    st = B.strategy(chi, 1e-10, sweeps=sweeps)
+    out, _ = ctx.zmpo_apply(zU, zv, st)  # warm-up
+    out.destroy()
+    times = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out, _ = ctx.zmpo_apply(zU, zv, st)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        last = out
+    info = ctx.last_info()
+    su = sweeps * 2 * (n - 1)
+    sec = float(np.median(times))
+    res = {"metric": "site-updates/s, complex MPO·MPS apply+simplify (FP64)", "unit": "site-updates/s",
+           "value": su / sec, "dtype": "c128", "data": "synthetic", "steps": len(times),
+           "ms_per_step": 1e3 * sec,
+           "config": {"workload": f"random complex MPO D={D} on random complex MPS n={n} chi={chi}, max bond {chi}, "
+                                  f"tol 1e-10, {sweeps} sweeps", "site_updates_per_step": su}}
+    if not args.no_cpu:
+        from oracle import dense  # noqa: F401
+        from oracle import zmps as oz
+        ref, nref, _ = oz.apply_simplify(U, v, chi, 1e-10, sweeps=sweeps)
+        got = last.read()
+        ov = abs(oz.scprod(got, ref))
+        res["rel_norm_err"] = abs(info["norm"] - nref) / nref
+        res["fidelity_loss"] = float(1 - ov / (info["norm"] * nref))
+        (dt, cores, reps), both = time_oracle(lambda: oz.apply_simplify(U, v, chi, 1e-10, sweeps=sweeps),
+                                              args.cpu_seconds)
+        res["cpu_baseline"] = {"value": su / dt, "unit": "site-updates/s", "cores": int(cores), "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"{reps} complex oracle runs of the same workload on the faster of all BLAS "
+                                         f"threads and one thread",
+                               "value_all_threads": su / both["s_per_call_all_threads"],
+                               "value_1_thread": su / both["s_per_call_1_thread"]}
+    print(json.dumps(res))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -393,6 +453,9 @@ def main():
         return
     if args.diffusion:
         diffusion_leg(args)
+        return
+    if args.complex:
+        complex_leg(args)
         return
 
     import numpy as np

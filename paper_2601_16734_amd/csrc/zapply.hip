@@ -163,12 +163,23 @@ __global__ __launch_bounds__(256) void znorm2_kernel(const double2* x, long long
     if (threadIdx.x == 0) *out = part[0];
 }
 
-constexpr int ZJ_NT = 256;          // threads of the Jacobi workgroup (16 groups of 16 lanes)
+constexpr int ZJ_NT = 1024;         // threads of the Jacobi workgroup (64 groups of 16 lanes)
 constexpr int ZJ_MAX_SWEEPS = 60;
 
-__device__ __forceinline__ double group_sum16(double v) {
-    for (int m = 8; m > 0; m >>= 1) v += __shfl_xor(v, m, 16);
-    return v;
+// Cross-lane move inside a row of 16 lanes (DPP) for a double, and the sum
+// over the row's 16 lanes (every lane ends with the same value).
+template <int CTRL>
+__device__ __forceinline__ double zdpp(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double group_sum16(double x) {
+    x += zdpp<0xB1>(x);   // lane ^ 1
+    x += zdpp<0x4E>(x);   // lane ^ 2
+    x += zdpp<0x141>(x);  // half-row mirror
+    x += zdpp<0x140>(x);  // row mirror
+    return x;
 }
 
 // Complex one-sided Jacobi SVD of nv rows of length len (X, row-major) in one
@@ -178,9 +189,11 @@ __device__ __forceinline__ double group_sum16(double v) {
 // the rank rule (relative-norm tail summed from the smallest value, or
 // relative singular value), the discarded weight, and the kept rows
 // normalised into Q (r x len).  out_int = {rank, status}; out_dbl = {delta}.
+// basis (nullable, len x len): every normalised row when the rows span C^len,
+// else the identity -- the warm start of the next factorization of the bond.
 __global__ __launch_bounds__(ZJ_NT) void zjacobi_kernel(const double2* X, int nv, int len, int max_rank, double tol,
                                                         int mode, double2* Q, double* sigma, int* out_int,
-                                                        double* out_dbl) {
+                                                        double* out_dbl, double2* basis) {
     extern __shared__ double2 zsm[];
     double2* W = zsm;                               // nv x len
     double* nrm = (double*)(W + (size_t)nv * len);  // nv
@@ -334,6 +347,17 @@ __global__ __launch_bounds__(ZJ_NT) void zjacobi_kernel(const double2* X, int nv
         const double2 w = W[(size_t)perm[i] * len + l];
         Q[e] = s > 0.0 ? make_double2(w.x / s, w.y / s) : make_double2(l == i ? 1.0 : 0.0, 0.0);
     }
+    if (!basis) return;
+    const bool full = nv >= len && sig[len - 1] > 0.0;
+    for (long long e = tid; e < (long long)len * len; e += ZJ_NT) {
+        const int i = (int)(e / len), l = (int)(e % len);
+        if (full) {
+            const double2 w = W[(size_t)perm[i] * len + l];
+            basis[e] = make_double2(w.x / sig[i], w.y / sig[i]);
+        } else {
+            basis[e] = make_double2(i == l ? 1.0 : 0.0, 0.0);
+        }
+    }
 }
 
 int blocks_for(long long n) { return (int)std::max<long long>(1, std::min<long long>(2048, (n + 255) / 256)); }
@@ -352,6 +376,13 @@ struct ZApply {
     std::vector<int> d, D, cv, chi, cap;
     std::vector<double2*> psi, Lenv, Renv;
     double2 *theta = nullptr, *x1 = nullptr, *x2 = nullptr, *xl = nullptr, *xr = nullptr, *jx = nullptr, *Q = nullptr;
+    double2* jx2 = nullptr;
+    // per bond: the basis the last split there left (len x len of that split,
+    // the identity when its rows did not span) and that len (0: none); the next
+    // split at the bond, whose vectors are that len in number, is pre-rotated
+    // by its conjugate
+    std::vector<double2*> basis;
+    std::vector<int> basis_dim;
     double *sigma = nullptr, *dbl = nullptr;
     int* ints = nullptr;
     int* host_ints = nullptr;
@@ -403,11 +434,21 @@ struct ZApply {
 
     // Rows of X (nv x ln) orthogonalised; Q receives the r kept normalised rows.
     hipError_t svd_rows(const double2* X, int nv, int ln, int max_rank, double tol, int mode, int* r_out,
-                        double* delta_out) {
+                        double* delta_out, int bond = -1) {
         const size_t shm = zjacobi_lds(nv, ln);
         if (shm > lds_limit) return hipErrorInvalidValue;
+        double2* bout = nullptr;
+        if (bond >= 0) {
+            if (basis_dim[bond] == nv) {  // warm start: conj(basis) X has nearly orthogonal rows
+                hipError_t e = mm(basis[bond], X, jx2, nv, ln, nv, ZK, ZN);
+                if (e != hipSuccess) return e;
+                X = jx2;
+            }
+            bout = basis[bond];
+            basis_dim[bond] = ln;
+        }
         hipLaunchKernelGGL(zjacobi_kernel, dim3(1), dim3(ZJ_NT), shm, s, X, nv, ln, max_rank, tol, mode, Q, sigma,
-                           ints, dbl);
+                           ints, dbl, bout);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(host_ints, ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -460,7 +501,7 @@ struct ZApply {
         double delta = 0.0;
         if (ltr) {  // left isometry: rows of theta^T are u_j^T
             e = transpose(theta, jx, a * s1, t1 * cc);
-            if (e == hipSuccess) e = svd_rows(jx, t1 * cc, a * s1, mr, st.tol, st.trunc_mode, &r, &delta);
+            if (e == hipSuccess) e = svd_rows(jx, t1 * cc, a * s1, mr, st.tol, st.trunc_mode, &r, &delta, k);
             if (e == hipSuccess) e = transpose(Q, psi[k], r, a * s1);                         // psi_k = U
             if (e == hipSuccess) e = mm(Q, theta, psi[k + 1], r, t1 * cc, a * s1, ZK, ZN);  // U^H theta
             if (e != hipSuccess) return e;
@@ -468,7 +509,7 @@ struct ZApply {
             deltas.push_back(delta);
             return env_L(k);
         }
-        e = svd_rows(theta, a * s1, t1 * cc, mr, st.tol, st.trunc_mode, &r, &delta);  // rows v_j^H
+        e = svd_rows(theta, a * s1, t1 * cc, mr, st.tol, st.trunc_mode, &r, &delta, k);  // rows v_j^H
         if (e == hipSuccess)
             e = hipMemcpyAsync(psi[k + 1], Q, sizeof(double2) * (size_t)r * t1 * cc, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = mm(theta, Q, psi[k], a * s1, r, t1 * cc, ZN, ZH);  // theta V
@@ -528,7 +569,14 @@ struct ZApply {
             ok = ok && (Lenv[k] = alloc<double2>((size_t)cap[k] * D[k] * cv[k]));
             ok = ok && (Renv[k] = alloc<double2>((size_t)cap[k] * D[k] * cv[k]));
         }
-        ok = ok && (theta = alloc<double2>(nth)) && (jx = alloc<double2>(nth)) && (Q = alloc<double2>(nth)) &&
+        basis.assign(std::max(0, L - 1), nullptr);
+        basis_dim.assign(std::max(0, L - 1), 0);
+        for (int k = 0; k + 1 < L; ++k) {
+            const size_t nb = std::max((size_t)cap[k] * d[k], (size_t)d[k + 1] * cap[k + 2]);
+            ok = ok && (basis[k] = alloc<double2>(nb * nb));
+        }
+        ok = ok && (theta = alloc<double2>(nth)) && (jx = alloc<double2>(nth)) && (jx2 = alloc<double2>(nth)) &&
+             (Q = alloc<double2>(nth)) &&
              (x1 = alloc<double2>(nx)) && (x2 = alloc<double2>(nx)) && (xl = alloc<double2>(nx)) &&
              (xr = alloc<double2>(nx)) && (sigma = alloc<double>(nth)) && (dbl = alloc<double>(4)) &&
              (ints = alloc<int>(4));
