@@ -54,6 +54,14 @@ def parse():
     ap.add_argument("--complex", action="store_true",
                     help="only measure the complex apply + compression (random complex MPO D=4 on a random complex "
                          "MPS n=20 chi=32, max bond 32, tol 1e-10, 4 sweeps) and print its JSON line")
+    ap.add_argument("--large", action="store_true",
+                    help="only measure the L=100 chi=256 XXZ workload (4 sweeps, FP64 and mixed contractions, the "
+                         "whole oracle as parity reference; several minutes) and print its JSON line")
+    ap.add_argument("--large-sweeps", type=int, default=4,
+                    help="sweeps of the --large workload (4 is the measured configuration; fewer for a profile)")
+    ap.add_argument("--batched", action="store_true",
+                    help="only measure the 512-chain QTT batch (batched by chi, graph-captured, FP64 and mixed; "
+                         "against a per-chain loop) and print its JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 4 device copies of MIB MiB (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -436,6 +444,253 @@ def complex_leg(args):
     ctx.close()
 
 
+def large_leg(args):
+    """The L=100 d=2 chi=256 chain under the nearest-neighbour XXZ-type MPO
+    (D=5, couplings uniform in [0.5, 1.5]): apply + compression at max bond
+    256, tol 1e-10, 4 sweeps, in FP64 and in the mixed contraction precisions
+    (FP64 factorizations throughout).  The two-site tensors are 512 x 512 in
+    the bulk, too large for one workgroup's LDS, so this measures the blocked
+    factorization path.  One apply per precision is timed, with
+    no warm-up (the one-time graph captures of the first call are well under
+    1% of an apply).  The whole oracle (same sweeps, all BLAS threads) is the
+    parity reference for every precision and the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    w = synth.workload_xxz()
+    L, sweeps = len(w.mps), args.large_sweeps
+    su = sweeps * 2 * (L - 1)
+    v = ctx.mps_create_device([torch.from_numpy(t).to("cuda") for t in w.mps])
+    U = ctx.mpo_create(w.mpo)
+    torch.cuda.synchronize()
+    caps = synth.bond_caps(L, 2, w.max_bond)
+    fact_flops = sum(svd_flops(2 * caps[k], 2 * caps[k + 2]) for k in list(range(L - 1)) * (2 * sweeps))
+    results, outs = {}, {}
+    precs = [p for p in args.precisions.split(",") if p != "bf16"]  # bf16 misses the 1e-8 bar (headline)
+    for prec in precs:
+        st = B.strategy(w.max_bond, w.tol, sweeps=sweeps, precision=prec)
+        torch.cuda.synchronize()
+        ctx.set_profiling(True)
+        t = time.perf_counter()
+        out, _ = ctx.mpo_apply(U, v, st)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        fact_ms, fact_n = ctx.kernel_time(0)
+        ctx.set_profiling(False)
+        info = ctx.last_info()
+        outs[prec] = out
+        results[prec] = {"ms_per_step": 1e3 * sec, "site_updates_per_s": su / sec, "norm": info["norm"],
+                         "factorization_ms_per_step": fact_ms, "factorizations_per_step": fact_n}
+        print(f"large leg: {prec} {su / sec:.1f} site-updates/s", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import mps as om
+        print(f"large leg: oracle, {sweeps} sweeps", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=sweeps)
+        dt = time.perf_counter() - t
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([tp.get("num_threads", 1) for tp in threadpool_info()] + [1])
+        except Exception:
+            threads = os.cpu_count()
+        cpu = {"value": su / dt, "unit": "site-updates/s", "cores": int(threads), "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"one full oracle run of the same workload ({su} site-updates, {dt:.0f} s, FP64 "
+                         f"NumPy/SciPy on all BLAS threads: the 512 x 512 SVDs gain from threads)"}
+        rr = om.scprod(ref.mps, ref.mps)
+        for prec, out in outs.items():
+            got = out.read()
+            r = results[prec]
+            r["rel_norm_err"] = abs(r["norm"] - ref.norm) / ref.norm
+            r["fidelity_loss"] = float(1 - abs(om.scprod(got, ref.mps)) / math.sqrt(om.scprod(got, got) * rr))
+            r["parity_1e-8"] = bool(r["rel_norm_err"] <= 1e-8 and r["fidelity_loss"] <= 1e-8)
+    for out in outs.values():
+        out.destroy()
+    fp64 = results.get("fp64")
+    ok = {p: r for p, r in results.items() if r.get("parity_1e-8", cpu is None)}
+    best_p = max(ok, key=lambda p: ok[p]["site_updates_per_s"]) if ok else "fp64"
+    best = results[best_p]
+    avg_ms = best["factorization_ms_per_step"] / max(1, best["factorizations_per_step"])
+    achieved = fact_flops / max(1, best["factorizations_per_step"]) / (avg_ms * 1e-3) / 1e12
+    line = {"metric": "site-updates/s, MPO·MPS apply+simplify, mixed vs FP64 GPU at <=1e-8 rel err",
+            "value": best["site_updates_per_s"], "unit": "site-updates/s", "n_gpus": 1, "steps": 1,
+            "warmup": 0, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[best_p], "data": "synthetic",
+            "config": {"workload": "XXZ-type MPO D=5 (couplings U[0.5,1.5]) on random MPS L=100 d=2 chi=256, "
+                                   f"max bond 256, tol 1e-10, {sweeps} sweeps", "site_updates_per_step": su,
+                       "precision": best_p},
+            "fp64_site_updates_per_s": fp64["site_updates_per_s"] if fp64 else None,
+            "speedup_vs_fp64": best["site_updates_per_s"] / fp64["site_updates_per_s"] if fp64 else None,
+            "per_precision": results,
+            "roofline": {"kernel": "one-sided Jacobi SVD of the 512 x 512 two-site tensors (blocked: block pairs "
+                                   "in LDS, one launch per round of the tournament over blocks)",
+                         "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                         "avg_factorization_ms": avg_ms,
+                         "share_of_step": best["factorization_ms_per_step"] / best["ms_per_step"]},
+            "cpu_baseline": cpu}
+    print(json.dumps(line))
+    ctx.close()
+
+
+def batched_leg(args):
+    """The 512-chain QTT batch (n uniform in [8, 30], chi uniform in
+    {4, 8, ..., 128}, FP32 N(0, 1/chi) entries, bond-3 Laplacian or bond-2
+    shift): every chain compressed at its own chi (tol 1e-10, 4 sweeps); the
+    chains are grouped by chi and each group runs as one batched, graph-captured
+    call.  The capture call is untimed; the timed call replays the graphs.
+    Compared with a loop of single-chain calls on the first 32 chains.  The
+    oracle checks a sample (the first 16 chains) and is timed on the first
+    chains in order, within the CPU budget, on one thread."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    ws = synth.workload_batch(count=512)
+    sweeps = 4
+    vs = [ctx.mps_create(w.mps, dtype=np.float32) for w in ws]
+    Us = [ctx.mpo_create(w.mpo) for w in ws]
+    groups = {}
+    for i, w in enumerate(ws):
+        groups.setdefault(w.max_bond, []).append(i)
+    steps_of = [sweeps * 2 * (w.meta["n"] - 1) for w in ws]
+    su = sum(steps_of)
+    precs = [p for p in args.precisions.split(",") if p != "bf16"]
+    results, outs = {}, {}
+    for prec in precs:
+        per_group, tot = {}, 0.0
+        outs[prec] = [None] * len(ws)
+        for cap, idx in sorted(groups.items()):
+            st = B.strategy(cap, 1e-10, sweeps=sweeps, precision=prec)
+            first, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)  # capture
+            for o in first:
+                o.destroy()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(1, args.steps)):
+                t = time.perf_counter()
+                got, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+                for j, i in enumerate(idx):
+                    if outs[prec][i] is not None:
+                        outs[prec][i].destroy()
+                    outs[prec][i] = got[j]
+            sec = float(np.median(times))
+            tot += sec
+            g_su = sum(steps_of[i] for i in idx)
+            per_group[str(cap)] = {"chains": len(idx), "site_updates": g_su, "ms": 1e3 * sec,
+                                   "site_updates_per_s": g_su / sec}
+        results[prec] = {"ms_per_step": 1e3 * tot, "site_updates_per_s": su / tot, "per_chi": per_group}
+        print(f"batched leg: {prec} {su / tot:.0f} site-updates/s", file=sys.stderr, flush=True)
+    # per-chain loop (single-problem calls) on the first 32 chains, FP64
+    loop_idx = list(range(32))
+    for i in loop_idx[:2]:  # warm-up
+        o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(ws[i].max_bond, 1e-10, sweeps=sweeps))
+        o.destroy()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in loop_idx:
+        o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(ws[i].max_bond, 1e-10, sweeps=sweeps))
+        o.destroy()
+    torch.cuda.synchronize()
+    loop_sec = time.perf_counter() - t
+    loop_rate = sum(steps_of[i] for i in loop_idx) / loop_sec
+    # the same 32 chains batched (FP64) for a like-for-like ratio
+    sub = {}
+    for i in loop_idx:
+        sub.setdefault(ws[i].max_bond, []).append(i)
+    sub_sec = 0.0
+    for cap, idx in sorted(sub.items()):
+        st = B.strategy(cap, 1e-10, sweeps=sweeps)
+        first, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
+        for o in first:
+            o.destroy()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        got, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
+        torch.cuda.synchronize()
+        sub_sec += time.perf_counter() - t
+        for o in got:
+            o.destroy()
+    sub_rate = sum(steps_of[i] for i in loop_idx) / sub_sec
+    cpu = None
+    if not args.no_cpu:
+        from oracle import mps as om
+        refs = {i: om.apply_simplify(ws[i].mpo, [t.astype(np.float64) for t in ws[i].mps], ws[i].max_bond,
+                                     1e-10, sweeps=sweeps) for i in range(16)}
+        for prec in precs:
+            worst_n, worst_f = 0.0, 0.0
+            for i, ref in refs.items():
+                got = outs[prec][i].read()
+                ne = abs(ctx.norm(outs[prec][i]) - ref.norm) / ref.norm
+                fl = float(1 - abs(om.scprod(got, ref.mps)) /
+                           math.sqrt(om.scprod(got, got) * om.scprod(ref.mps, ref.mps)))
+                worst_n, worst_f = max(worst_n, ne), max(worst_f, fl)
+            r = results[prec]
+            r["sample_rel_norm_err_max"], r["sample_fidelity_loss_max"] = worst_n, worst_f
+            r["parity_1e-8"] = bool(worst_n <= 1e-8 and worst_f <= 1e-8)
+        try:
+            from threadpoolctl import threadpool_limits
+        except Exception:
+            threadpool_limits = None
+        done_su, t0 = 0, time.perf_counter()
+        count = 0
+        for i, w in enumerate(ws):
+            mps64 = [t.astype(np.float64) for t in w.mps]
+            if threadpool_limits is not None:
+                with threadpool_limits(limits=1):
+                    om.apply_simplify(w.mpo, mps64, w.max_bond, 1e-10, sweeps=sweeps)
+            else:
+                om.apply_simplify(w.mpo, mps64, w.max_bond, 1e-10, sweeps=sweeps)
+            done_su += steps_of[i]
+            count += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": done_su / dt, "unit": "site-updates/s", "cores": 1 if threadpool_limits else os.cpu_count(),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"the first {count} chains of the batch in order ({done_su} site-updates, {dt:.1f} s), "
+                         f"FP64 NumPy/SciPy on one thread"}
+    for lst in outs.values():
+        for o in lst:
+            if o is not None:
+                o.destroy()
+    fp64 = results.get("fp64")
+    ok = {p: r for p, r in results.items() if r.get("parity_1e-8", cpu is None)}
+    best_p = max(ok, key=lambda p: ok[p]["site_updates_per_s"]) if ok else "fp64"
+    best = results[best_p]
+    line = {"metric": "site-updates/s, MPO·MPS apply+simplify, mixed vs FP64 GPU at <=1e-8 rel err",
+            "value": best["site_updates_per_s"], "unit": "site-updates/s", "n_gpus": 1, "steps": max(1, args.steps),
+            "warmup": 1, "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[best_p], "data": "synthetic",
+            "config": {"workload": "512 QTT chains, n uniform in [8,30], d=2, chi uniform in {4,...,128}, FP32 "
+                                   "entries, bond-3 Laplacian or bond-2 shift MPO, max bond chi, tol 1e-10, 4 sweeps; "
+                                   "batched by chi, graph-captured", "site_updates_per_step": su,
+                       "precision": best_p},
+            "fp64_site_updates_per_s": fp64["site_updates_per_s"] if fp64 else None,
+            "speedup_vs_fp64": best["site_updates_per_s"] / fp64["site_updates_per_s"] if fp64 else None,
+            "per_precision": results,
+            "per_chain_loop_first32_fp64": {"site_updates_per_s": loop_rate,
+                                            "batched_same_32_fp64_site_updates_per_s": sub_rate,
+                                            "batched_over_loop": sub_rate / loop_rate},
+            "cpu_baseline": cpu}
+    print(json.dumps(line))
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -456,6 +711,12 @@ def main():
         return
     if args.complex:
         complex_leg(args)
+        return
+    if args.large:
+        large_leg(args)
+        return
+    if args.batched:
+        batched_leg(args)
         return
 
     import numpy as np

@@ -91,9 +91,19 @@ __device__ __forceinline__ double row_sum4(double x) {
     x += dpp_mov<0x4E>(x);
     return x;
 }
+// Sum over a whole wave: the rows' sums, then the other rows' by lane swaps
+// (each step again adds equal partners in either order, so every lane ends
+// with the identical value).
+__device__ __forceinline__ double wave_sum(double x) {
+    x = row_sum16(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
 template <int G>
 __device__ __forceinline__ double group_sum(double x) {
-    if constexpr (G == 16) return row_sum16(x);
+    if constexpr (G == 64) return wave_sum(x);
+    else if constexpr (G == 16) return row_sum16(x);
     else if constexpr (G == 8) return row_sum8(x);
     else return row_sum4(x);
 }
@@ -129,6 +139,39 @@ __device__ __forceinline__ bool jacobi_needs_rotation(double a, double b, double
     return fabs(c) > tol * (a * __builtin_amdgcn_rsq(a)) * (b * __builtin_amdgcn_rsq(b));
 }
 
+// Copy nrows rows of len doubles from global memory (row j starts at
+// row_src(j)) into LDS rows of stride ld >= len, zero padded.  Each thread
+// issues LOADS independent loads before it stores any of them: the LDS stores
+// could alias a generic pointer's loads, so a plain copy loop would wait for
+// every load in turn.  Returns nonzero if a loaded value is not finite.
+template <int LOADS = 8, typename RowSrc>
+__device__ __forceinline__ int load_rows_to_lds(double* W, int nrows, int len, int ld, RowSrc row_src, int tid,
+                                                int nt) {
+    const int total = nrows * ld;
+    int bad = 0;
+    for (int base = 0; base < total; base += LOADS * nt) {
+        double v[LOADS];
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) {
+            const int e = base + u * nt + tid;
+            v[u] = 0.0;
+            if (e < total) {
+                const int j = e / ld, i = e - j * ld;
+                if (i < len) v[u] = row_src(j)[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < LOADS; ++u) {
+            const int e = base + u * nt + tid;
+            if (e < total) {
+                bad |= !isfinite(v[u]);
+                W[e] = v[u];
+            }
+        }
+    }
+    return bad;
+}
+
 __device__ __forceinline__ int pow2_ceil(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -139,7 +182,7 @@ __device__ __forceinline__ int pow2_ceil(int x) {
 // (nv doubles of LDS) holds their squared norms, recomputed exactly at the
 // start of every sweep and updated in between by the exact 2x2 relations
 // (a' = a - t c, b' = b + t c), so a pair needs one dot product only.
-// A group of G lanes (G = 4, 8 or 16, inside one DPP row) handles a pair;
+// A group of G lanes (G = 4, 8 or 16 inside one DPP row, or a whole wave) handles a pair;
 // the pairs of a round are disjoint and run concurrently.  E > 0: each lane
 // keeps its E elements of both vectors in registers between the dot product
 // and the rotation (rows zero padded to ld = G E); E = 0: generic strided loop.
@@ -167,7 +210,7 @@ __device__ __forceinline__ void rotate_acc(double* Jw, int nj, int p, int q, int
 template <int E, int G = 16, bool ACC = false>
 __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double floor2,
                              int true_len, int max_sweeps = JAC_MAX_SWEEPS, double* Jw = nullptr, int nj = 0) {
-    static_assert(G == 4 || G == 8 || G == 16, "group width");
+    static_assert(G == 4 || G == 8 || G == 16 || G == 64, "group width");
     static_assert(E > 0 || G == 16, "generic path uses 16-lane groups");
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
@@ -486,16 +529,8 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     if (Jw)
         for (int e = tid; e < nv * nv; e += LDS_NT) Jw[e] = (e / nv == e % nv) ? 1.0 : 0.0;
     __syncthreads();
-    int bad = 0;
-    for (int e = tid; e < nv * ld; e += LDS_NT) {
-        const int j = e / ld, i = e - j * ld;
-        double x = 0.0;
-        if (i < len) {
-            x = d.X[(size_t)j * len + i];
-            bad |= !isfinite(x);
-        }
-        W[e] = x;
-    }
+    const double* X = d.X;
+    const int bad = load_rows_to_lds(W, nv, len, ld, [=](int j) { return X + (size_t)j * len; }, tid, LDS_NT);
     if (bad) s_bad = 1;
     __syncthreads();
     if (s_bad) {
@@ -529,13 +564,20 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram, Jw);
 }
 
+// Threads of a blocked-path workgroup: G = 16 as the LDS kernel of class E;
+// whole-wave groups (rows of 257..1024 elements) take 16 waves.
+__host__ __device__ constexpr int panel_threads(int E, int G) { return G == 64 ? 1024 : lds_threads(E); }
+
 // One round of the blocked path: workgroup i takes the block pair of
 // tournament position i, orthogonalises the union in LDS, writes it back.
-// Batched launches index the factorization by blockIdx.y; a factorization
-// whose `done` flag is set (converged in an earlier sweep) exits at once.
-template <int E>
-__global__ __launch_bounds__(lds_threads(E)) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr, int rd) {
-    constexpr int NT = lds_threads(E);
+// Rows are zero padded to G E elements (E > 0), E held per lane by groups of
+// G lanes; E = 0 is the strided generic loop.  Batched launches index the
+// factorization by blockIdx.y; a factorization whose `done` flag is set
+// (converged in an earlier sweep) exits at once.
+template <int E, int G = 16>
+__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr,
+                                                                          int rd) {
+    constexpr int NT = panel_threads(E, G);
     extern __shared__ double sm[];
     __shared__ int s_flag, s_bad;
     __shared__ double s_nrm[64];
@@ -544,8 +586,8 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_panel_kernel(JacobiDesc
     if (rd >= nblk2 - 1 || (int)blockIdx.x >= nblk2 / 2) return;
     if (d.done && *d.done) return;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
-    // rows zero padded to 16 E in LDS for the register path (E > 0)
-    const int ld = E > 0 ? 16 * E : len;
+    // rows zero padded to G E in LDS for the register path (E > 0)
+    const int ld = E > 0 ? G * E : len;
     const int bp = tourney(blockIdx.x, rd, nblk2), bq = tourney(nblk2 - 1 - blockIdx.x, rd, nblk2);
     // vectors of the two blocks that exist
     int idx[2], cnt[2];
@@ -558,17 +600,10 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_panel_kernel(JacobiDesc
     const int tid = threadIdx.x;
     if (tid == 0) s_bad = 0;
     __syncthreads();
-    int bad = 0;
-    for (size_t e = tid; e < (size_t)nloc * ld; e += NT) {
-        const int j = (int)(e / ld), l = (int)(e % ld);
-        const int gj = j < cnt[0] ? idx[0] + j : idx[1] + (j - cnt[0]);
-        double x = 0.0;
-        if (l < len) {
-            x = d.X[(size_t)gj * len + l];
-            bad |= !isfinite(x);
-        }
-        sm[e] = x;
-    }
+    const double* X = d.X;
+    const int i0 = idx[0], i1 = idx[1], c0 = cnt[0];
+    const int bad = load_rows_to_lds(
+        sm, nloc, len, ld, [=](int j) { return X + (size_t)(j < c0 ? i0 + j : i1 + (j - c0)) * len; }, tid, NT);
     if (bad) s_bad = 1;
     __syncthreads();
     if (s_bad) {
@@ -576,13 +611,13 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_panel_kernel(JacobiDesc
         return;
     }
     // one inner sweep per round: the outer tournament then acts as one cyclic ordering
-    const bool any = jacobi_orth_t<E, 16>(sm, nloc, E > 0 ? ld : len, ld, s_nrm, &s_flag,
-                                          zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
+    const bool any = jacobi_orth_t<E, G>(sm, nloc, E > 0 ? ld : len, ld, s_nrm, &s_flag,
+                                         zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
     if (!any) return;
-    for (size_t e = tid; e < (size_t)nloc * ld; e += NT) {
-        const int j = (int)(e / ld), l = (int)(e % ld);
+    for (int e = tid; e < nloc * ld; e += NT) {
+        const int j = e / ld, l = e - j * ld;
         if (l >= len) continue;
-        const int gj = j < cnt[0] ? idx[0] + j : idx[1] + (j - cnt[0]);
+        const int gj = j < c0 ? i0 + j : i1 + (j - c0);
         d.X[(size_t)gj * len + l] = sm[e];
     }
     if (tid == 0 && d.conv) atomicOr(d.conv, 1);
@@ -656,7 +691,7 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const 
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     jacobi_select(d.X, nv, len, len, sig_raw, sig_sorted, perm_s, d, &s_delta);
-    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // sweeps of the global-memory paths are not logged
+    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // the single path's host loop sets its count after
     for (int j = threadIdx.x; j < nv; j += JT) d.perm[j] = perm_s[j];
 }
 
@@ -681,6 +716,7 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d0, const 
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
 
 // Batched blocked path, between sweeps: a factorization that rotated nothing
 // in the sweep just finished is done; clear the rotation flags.
@@ -743,7 +779,8 @@ hipError_t jacobi_init(int device) {
                              (const void*)jacobi_lds_kernel<8, true>,  (const void*)jacobi_lds_kernel<16, true>,
                              (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
                              (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
-                             (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>};
+                             (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>,
+                             (const void*)jacobi_panel_kernel<8, 64>, (const void*)jacobi_panel_kernel<16, 64>};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -776,23 +813,69 @@ bool jacobi_fits_lds(int nvec_cap, int len_cap, bool acc) {
 int jacobi_lds_class(int len_cap) { return elems_for(len_cap); }
 size_t jacobi_lds_bytes(int nvec_cap, int len_cap, bool acc) { return lds_need(nvec_cap, len_cap, acc); }
 
-// Rows per block of the batched blocked path and the LDS its workgroups need:
-// two blocks of rows of length 16 E (zero padded, register path) or len_cap.
-static size_t panel_ld(int len_cap) {
-    const int e = elems_for(len_cap);
-    return e > 0 ? 16 * (size_t)e : (size_t)len_cap;
+// Shape of the blocked path for rows of at most len_cap elements: E elements
+// per lane held by groups of G lanes, rows zero padded to ld = G E (E = 0:
+// unpadded, strided loop), bs rows per block (a workgroup takes two blocks in
+// LDS).  Rows of 257..1024 elements take a whole wave per pair (E = 8 or 16),
+// with a power-of-two block so that the home/away ordering applies.
+struct PanelShape {
+    int E, G, ld, threads, bs;
+};
+
+static PanelShape panel_shape(int len_cap) {
+    PanelShape p{};
+    const size_t room = (size_t)std::max(0, g_lds_bytes - 4096);
+    if (len_cap > 256 && len_cap <= 1024) {
+        p.G = 64;
+        p.E = len_cap <= 512 ? 8 : 16;
+        p.ld = p.G * p.E;
+        p.threads = panel_threads(p.E, p.G);
+        int bs = (int)std::min<size_t>(p.threads / p.G, room / (2 * sizeof(double) * (size_t)p.ld));
+        int b2 = 1;
+        while (2 * b2 <= bs) b2 <<= 1;
+        p.bs = bs >= 1 ? b2 : 0;
+    } else {
+        p.G = 16;
+        p.E = elems_for(len_cap);
+        p.ld = p.E > 0 ? 16 * p.E : len_cap;
+        p.threads = panel_threads(p.E, p.G);
+        p.bs = (int)std::min<size_t>(32, room / (2 * sizeof(double) * (size_t)p.ld));
+    }
+    return p;
 }
 
-size_t jacobi_panel_bytes(int len_cap, int bs) { return sizeof(double) * 2 * (size_t)bs * panel_ld(len_cap); }
+size_t jacobi_panel_bytes(int len_cap, int bs) {
+    return sizeof(double) * 2 * (size_t)bs * (size_t)panel_shape(len_cap).ld;
+}
 
 void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) {
-    int bs = (int)((g_lds_bytes - 4096) / (2 * sizeof(double) * panel_ld(len_cap)));
-    if (bs > 32) bs = 32;
-    if (bs < 1) bs = 1;
+    const int bs = std::max(1, panel_shape(len_cap).bs);
     int nblk = (nvec_cap + bs - 1) / bs;
     if (nblk & 1) ++nblk;
+    if (nblk < 2) nblk = 2;
     *bs_out = bs;
     *nblk_out = nblk;
+}
+
+// One launch of the blocked path's round rd for the shape of len_cap.
+static void launch_panel_round(const PanelShape& ps, dim3 grid, size_t shm, hipStream_t s, const JacobiDesc& d0,
+                               const JacobiDesc* arr, int rd) {
+    const dim3 block(ps.threads);
+    if (ps.G == 64) {
+        if (ps.E == 8)
+            hipLaunchKernelGGL((jacobi_panel_kernel<8, 64>), grid, block, shm, s, d0, arr, rd);
+        else
+            hipLaunchKernelGGL((jacobi_panel_kernel<16, 64>), grid, block, shm, s, d0, arr, rd);
+        return;
+    }
+    switch (ps.E) {
+        case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, grid, block, shm, s, d0, arr, rd); break;
+        case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, grid, block, shm, s, d0, arr, rd); break;
+        case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, grid, block, shm, s, d0, arr, rd); break;
+        case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, grid, block, shm, s, d0, arr, rd); break;
+        case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, grid, block, shm, s, d0, arr, rd); break;
+        default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, grid, block, shm, s, d0, arr, rd); break;
+    }
 }
 
 size_t jacobi_work_doubles(int, int) { return 0; }
@@ -864,13 +947,29 @@ static void enqueue_round_sweep(const JacobiDesc& dd, int rounds, int ew, dim3 g
     }
 }
 
+// One sweep of the single-problem blocked path: flag reset + one launch per
+// round of the tournament over blocks.
+static void enqueue_panel_sweep(const JacobiDesc& dd, const PanelShape& ps, size_t shm, int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
+    for (int rd = 0; rd < dd.nblk - 1; ++rd) launch_panel_round(ps, dim3(dd.nblk / 2), shm, s, dd, nullptr, rd);
+}
+
+// ew > 0: a sweep of the round kernel with ew elements per lane; ew == 0: a
+// sweep of the blocked path (ps, shm).
 static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, dim3 grid, int* flags,
-                                    hipGraphExec_t* out) {
+                                    hipGraphExec_t* out, const PanelShape* ps = nullptr, size_t shm = 0) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::string key;
     key_add(key, dev);
+    key_add(key, dd.bs);
+    key_add(key, dd.nblk);
+    key_add(key, shm);
+    if (ps) {
+        key_add(key, ps->E);
+        key_add(key, ps->G);
+    }
     key_add(key, dd.X);
     key_add(key, dd.dims_in);
     key_add(key, dd.nvec);
@@ -899,7 +998,10 @@ static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, di
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        enqueue_round_sweep(dd, rounds, ew, grid, flags, cs);
+        if (ew > 0)
+            enqueue_round_sweep(dd, rounds, ew, grid, flags, cs);
+        else
+            enqueue_panel_sweep(dd, *ps, shm, flags, cs);
         e = hipGetLastError();
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
@@ -925,19 +1027,30 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     if (d.accumulate) return hipErrorInvalidValue;  // accumulation is an LDS-kernel feature
     if (nvec_cap > SEL_MAX) return hipErrorInvalidValue;
     if (len_cap > 64 * 32) return hipErrorInvalidValue;
-    // global-memory path: one launch per round of the tournament; `flags` is
-    // one device int used as the "rotated" flag, read by the host after every sweep
+    // `flags` is one device int used as the "rotated" flag, read by the host after every sweep
     JacobiDesc dd = d;
     dd.conv = flags;
     dd.done = nullptr;
     if (!dd.fro2) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
-    const int P = (nvec_cap + 1) / 2, rounds = 2 * P - 1;
-    const dim3 grid((P + 3) / 4);
-    const int ew = len_cap <= 128 ? 2 : len_cap <= 256 ? 4 : len_cap <= 512 ? 8 : len_cap <= 1024 ? 16 : 32;
     hipGraphExec_t exec = nullptr;
-    hipError_t ge = round_sweep_graph(dd, rounds, ew, grid, flags, &exec);
-    if (ge != hipSuccess) return ge;
+    const PanelShape ps = panel_shape(len_cap);
+    if (len_cap <= 1024 && ps.bs >= 1) {
+        // blocked path: a tournament over blocks of rows, each block pair
+        // orthogonalised in LDS (one inner sweep), one launch per round
+        jacobi_panel_params(nvec_cap, len_cap, &dd.bs, &dd.nblk);
+        const size_t shm = jacobi_panel_bytes(len_cap, dd.bs);
+        hipError_t ge = round_sweep_graph(dd, dd.nblk - 1, 0, dim3(dd.nblk / 2), flags, &exec, &ps, shm);
+        if (ge != hipSuccess) return ge;
+    } else {
+        // rows beyond 1024 elements: one wave per pair from global memory, one
+        // launch per round of the tournament over single rows
+        const int P = (nvec_cap + 1) / 2, rounds = 2 * P - 1;
+        const dim3 grid((P + 3) / 4);
+        const int ew = len_cap <= 128 ? 2 : len_cap <= 256 ? 4 : len_cap <= 512 ? 8 : len_cap <= 1024 ? 16 : 32;
+        hipError_t ge = round_sweep_graph(dd, rounds, ew, grid, flags, &exec);
+        if (ge != hipSuccess) return ge;
+    }
     int sweep = 0;
     bool converged = false;
     for (; sweep < ROUND_MAX_SWEEPS; ++sweep) {
@@ -955,6 +1068,8 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     }
     if (!converged && dd.status) hipLaunchKernelGGL(or_int_kernel, dim3(1), dim3(1), 0, s, dd.status, 2);
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
+    // sweeps that rotated (the last, converged one did not)
+    if (dd.log_sweeps) hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, dd.log_sweeps, sweep);
     const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
     return hipGetLastError();
@@ -978,19 +1093,10 @@ hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max
     JacobiDesc none{};
     hipLaunchKernelGGL(jacobi_reset_kernel, dim3(1), dim3(256), 0, s, arr, count);
     hipLaunchKernelGGL(fro2_kernel, dim3(count), dim3(JT), 0, s, none, arr);
-    const int E = elems_for(len_cap);
-    const dim3 grid(max_pairs, count), block(lds_threads(E));
+    const PanelShape ps = panel_shape(len_cap);
+    const dim3 grid(max_pairs, count);
     for (int sw = 0; sw < sweeps; ++sw) {
-        for (int rd = 0; rd < max_nblk - 1; ++rd) {
-            switch (E) {
-                case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, grid, block, shm, s, none, arr, rd); break;
-                case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, grid, block, shm, s, none, arr, rd); break;
-                case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, grid, block, shm, s, none, arr, rd); break;
-                case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, grid, block, shm, s, none, arr, rd); break;
-                case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, grid, block, shm, s, none, arr, rd); break;
-                default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, grid, block, shm, s, none, arr, rd); break;
-            }
-        }
+        for (int rd = 0; rd < max_nblk - 1; ++rd) launch_panel_round(ps, grid, shm, s, none, arr, rd);
         hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(1), dim3(256), 0, s, arr, count);
     }
     hipLaunchKernelGGL(jacobi_check_done_kernel, dim3(1), dim3(256), 0, s, arr, count);

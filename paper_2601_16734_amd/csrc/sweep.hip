@@ -1036,6 +1036,14 @@ int run_autotune(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_s
 
 constexpr int PANEL_SWEEPS_BATCHED = 40;
 
+// Kernel nodes one batched graph may hold.  The blocked factorization enqueues
+// its whole sweep budget (rounds x sweeps) per step, so a chain with two-site
+// tensors far beyond the LDS multiplies the graph: the 512-chain QTT batch
+// needs about 8e4 nodes; a single L = 100, chi = 256 chain about 2.2e5 per
+// sweep, and such a capture ended the process on the host.  Larger batches
+// are refused (such chains belong on the single-problem path).
+constexpr long long MAX_GRAPH_KERNELS = 100000;
+
 struct IntSetDesc {
     int* dst;
     int val;
@@ -1198,7 +1206,7 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                 // LDS-resident factorizations grouped by register class; the rest blocked
                 std::map<int, std::vector<JacobiDesc>> lds;
                 std::map<int, size_t> lds_shm;
-                std::vector<JacobiDesc> panel;
+                std::vector<const Op*> blocked;
                 Launch pl;
                 pl.kind = OP_JAC;
                 pl.panel = true;
@@ -1210,15 +1218,21 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                         lds[key].push_back(o->jd);
                         lds_shm[key] = std::max(lds_shm[key], jacobi_lds_bytes(o->cap0, o->cap1, acc));
                     } else {
-                        JacobiDesc d = o->jd;
-                        jacobi_panel_params(o->cap0, o->cap1, &d.bs, &d.nblk);
-                        panel.push_back(d);
-                        pl.max_pairs = std::max(pl.max_pairs, d.nblk / 2);
-                        pl.max_nblk = std::max(pl.max_nblk, d.nblk);
-                        pl.max_rows = std::max(pl.max_rows, d.basis ? std::max(o->cap0, o->cap1) : o->cap0);
+                        blocked.push_back(o);
                         pl.cap1 = std::max(pl.cap1, o->cap1);
-                        pl.shm = std::max(pl.shm, jacobi_panel_bytes(o->cap1, d.bs));
                     }
+                }
+                // the blocked launch's row layout follows its longest rows: every
+                // factorization in it takes that shape's block size
+                std::vector<JacobiDesc> panel;
+                for (const Op* o : blocked) {
+                    JacobiDesc d = o->jd;
+                    jacobi_panel_params(o->cap0, pl.cap1, &d.bs, &d.nblk);
+                    panel.push_back(d);
+                    pl.max_pairs = std::max(pl.max_pairs, d.nblk / 2);
+                    pl.max_nblk = std::max(pl.max_nblk, d.nblk);
+                    pl.max_rows = std::max(pl.max_rows, d.basis ? std::max(o->cap0, o->cap1) : o->cap0);
+                    pl.shm = std::max(pl.shm, jacobi_panel_bytes(pl.cap1, d.bs));
                 }
                 for (auto& cls : lds) {
                     Launch l2;
@@ -1279,6 +1293,18 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
             }
         }
     }
+}
+
+// Kernels enqueue_launches issues for ls (an upper bound).
+static long long graph_kernels(const std::vector<Launch>& ls) {
+    long long n = 1;  // the gather
+    for (const Launch& l : ls) {
+        if (l.kind == OP_JAC && l.panel)
+            n += 5 + (long long)PANEL_SWEEPS_BATCHED * l.max_nblk;
+        else
+            n += 2;
+    }
+    return n;
 }
 
 static hipError_t enqueue_launches(const std::vector<Launch>& ls, char* dev, hipStream_t s) {
@@ -1374,6 +1400,14 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
         DescArena da;
         std::vector<Launch> launches;
         build_launches(ops, da, launches);
+        const long long nodes = graph_kernels(launches);
+        if (nodes > MAX_GRAPH_KERNELS) {
+            batch_cache_free(c);
+            return fail(c, SMPS_EUNSUPPORTED,
+                        "the batch would capture " + std::to_string(nodes) + " kernels (limit " +
+                            std::to_string(MAX_GRAPH_KERNELS) +
+                            "); chains whose two-site tensors exceed the LDS by far take the single-problem path");
+        }
         // gather of the per-problem results into one buffer
         size_t stride = 0;
         for (int i = 0; i < n; ++i) stride = std::max(stride, (size_t)(4 + plans[i].L + 1));

@@ -134,3 +134,15 @@ def test_single_blocked_path_vs_oracle(ctx, qtt_sample):
     got = out.read()
     assert rel_norm_err(ctx.last_info()["norm"], ref.norm) <= 1e-8
     assert cross_fidelity_loss(got, ref.mps) <= 1e-8
+
+
+def test_batched_refuses_a_graph_beyond_its_kernel_limit(ctx):
+    # the L=100 chi=256 chain's 512 x 512 two-site tensors take the blocked
+    # factorization, whose full sweep budget per step would put about 2.2e5
+    # kernels in one graph: refused before anything is captured
+    w = synth.workload_xxz()
+    v, U = ctx.mps_create(w.mps), ctx.mpo_create(w.mpo)
+    with pytest.raises(B.SmpsError) as e:
+        ctx.mpo_apply_batched([U], [v], B.strategy(256, 1e-10, sweeps=1))
+    assert e.value.code == B.EUNSUPPORTED
+    assert "limit" in str(e.value)
