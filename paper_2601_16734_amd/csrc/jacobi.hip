@@ -100,9 +100,16 @@ __device__ __forceinline__ double wave_sum(double x) {
     x += __shfl_xor(x, 32, 64);
     return x;
 }
+// Sum over a half wave (two DPP rows): the rows' sums, then the partner row's.
+__device__ __forceinline__ double half_wave_sum(double x) {
+    x = row_sum16(x);
+    x += __shfl_xor(x, 16, 64);
+    return x;
+}
 template <int G>
 __device__ __forceinline__ double group_sum(double x) {
     if constexpr (G == 64) return wave_sum(x);
+    else if constexpr (G == 32) return half_wave_sum(x);
     else if constexpr (G == 16) return row_sum16(x);
     else if constexpr (G == 8) return row_sum8(x);
     else return row_sum4(x);
@@ -182,7 +189,7 @@ __device__ __forceinline__ int pow2_ceil(int x) {
 // (nv doubles of LDS) holds their squared norms, recomputed exactly at the
 // start of every sweep and updated in between by the exact 2x2 relations
 // (a' = a - t c, b' = b + t c), so a pair needs one dot product only.
-// A group of G lanes (G = 4, 8 or 16 inside one DPP row, or a whole wave) handles a pair;
+// A group of G lanes (G = 4, 8 or 16 inside one DPP row, two rows, or a whole wave) handles a pair;
 // the pairs of a round are disjoint and run concurrently.  E > 0: each lane
 // keeps its E elements of both vectors in registers between the dot product
 // and the rotation (rows zero padded to ld = G E); E = 0: generic strided loop.
@@ -210,7 +217,7 @@ __device__ __forceinline__ void rotate_acc(double* Jw, int nj, int p, int q, int
 template <int E, int G = 16, bool ACC = false>
 __device__ int jacobi_orth_t(double* W, int nv, int len, int ld, double* nrm, int* s_flag, double floor2,
                              int true_len, int max_sweeps = JAC_MAX_SWEEPS, double* Jw = nullptr, int nj = 0) {
-    static_assert(G == 4 || G == 8 || G == 16 || G == 64, "group width");
+    static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group width");
     static_assert(E > 0 || G == 16, "generic path uses 16-lane groups");
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
@@ -565,8 +572,11 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
 }
 
 // Threads of a blocked-path workgroup: G = 16 as the LDS kernel of class E;
-// whole-wave groups (rows of 257..1024 elements) take 16 waves.
-__host__ __device__ constexpr int panel_threads(int E, int G) { return G == 64 ? 1024 : lds_threads(E); }
+// wider groups (rows of 257..1024 elements) one group per pair of a 32-row
+// block pair (16 pairs) or of a 16-row one (8 pairs).
+__host__ __device__ constexpr int panel_threads(int E, int G) {
+    return G == 64 ? 1024 : G == 32 ? 512 : lds_threads(E);
+}
 
 // One round of the blocked path: workgroup i takes the block pair of
 // tournament position i, orthogonalises the union in LDS, writes it back.
@@ -780,7 +790,7 @@ hipError_t jacobi_init(int device) {
                              (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
                              (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
                              (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>,
-                             (const void*)jacobi_panel_kernel<8, 64>, (const void*)jacobi_panel_kernel<16, 64>};
+                             (const void*)jacobi_panel_kernel<16, 32>, (const void*)jacobi_panel_kernel<16, 64>};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -816,7 +826,9 @@ size_t jacobi_lds_bytes(int nvec_cap, int len_cap, bool acc) { return lds_need(n
 // Shape of the blocked path for rows of at most len_cap elements: E elements
 // per lane held by groups of G lanes, rows zero padded to ld = G E (E = 0:
 // unpadded, strided loop), bs rows per block (a workgroup takes two blocks in
-// LDS).  Rows of 257..1024 elements take a whole wave per pair (E = 8 or 16),
+// LDS).  Rows of 257..1024 elements keep 16 elements per lane in half-wave or
+// whole-wave groups (the per-pair reduction and rotation cost the same
+// instructions whatever the row length, so long rows per lane amortise them),
 // with a power-of-two block so that the home/away ordering applies.
 struct PanelShape {
     int E, G, ld, threads, bs;
@@ -826,8 +838,8 @@ static PanelShape panel_shape(int len_cap) {
     PanelShape p{};
     const size_t room = (size_t)std::max(0, g_lds_bytes - 4096);
     if (len_cap > 256 && len_cap <= 1024) {
-        p.G = 64;
-        p.E = len_cap <= 512 ? 8 : 16;
+        p.G = len_cap <= 512 ? 32 : 64;
+        p.E = 16;
         p.ld = p.G * p.E;
         p.threads = panel_threads(p.E, p.G);
         int bs = (int)std::min<size_t>(p.threads / p.G, room / (2 * sizeof(double) * (size_t)p.ld));
@@ -862,10 +874,11 @@ static void launch_panel_round(const PanelShape& ps, dim3 grid, size_t shm, hipS
                                const JacobiDesc* arr, int rd) {
     const dim3 block(ps.threads);
     if (ps.G == 64) {
-        if (ps.E == 8)
-            hipLaunchKernelGGL((jacobi_panel_kernel<8, 64>), grid, block, shm, s, d0, arr, rd);
-        else
-            hipLaunchKernelGGL((jacobi_panel_kernel<16, 64>), grid, block, shm, s, d0, arr, rd);
+        hipLaunchKernelGGL((jacobi_panel_kernel<16, 64>), grid, block, shm, s, d0, arr, rd);
+        return;
+    }
+    if (ps.G == 32) {
+        hipLaunchKernelGGL((jacobi_panel_kernel<16, 32>), grid, block, shm, s, d0, arr, rd);
         return;
     }
     switch (ps.E) {
