@@ -146,3 +146,23 @@ def test_batched_refuses_a_graph_beyond_its_kernel_limit(ctx):
         ctx.mpo_apply_batched([U], [v], B.strategy(256, 1e-10, sweeps=1))
     assert e.value.code == B.EUNSUPPORTED
     assert "limit" in str(e.value)
+
+
+def test_batched_blocked_launch_with_long_and_short_rows(ctx):
+    # chi = 256 and chi = 128 chains in one batch: at the bulk steps their
+    # blocked factorizations share a launch shaped for the longer (512) rows,
+    # the shorter rows zero padded; each result must match its oracle run
+    rng = np.random.default_rng(141)
+    ws = []
+    for chi in (256, 128):
+        mps = synth.random_mps(rng, 16, 2, chi)
+        mpo = synth.random_mpo(rng, 16, 2, 2)
+        ws.append(synth.Workload(f"chi{chi}", mps, mpo, 256, 1e-10))
+    vs, Us = upload(ctx, ws)
+    outs, errs = ctx.mpo_apply_batched(Us, vs, B.strategy(256, 1e-10, sweeps=1))
+    for i, w in enumerate(ws):
+        ref = om.apply_simplify(w.mpo, w.mps, 256, 1e-10, sweeps=1)
+        got = outs[i].read()
+        assert [1] + [t.shape[2] for t in got] == ref.ranks, i
+        assert rel_norm_err(ctx.norm(outs[i]), ref.norm) <= 1e-10, i
+        assert cross_fidelity_loss(got, ref.mps) <= 1e-10, i
