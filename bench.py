@@ -200,7 +200,8 @@ def learned_rank(args):
     def measure(mpo, mps, max_bond, tol, sweeps):
         U, v = ctx.mpo_create(mpo), ctx.mps_create(mps)
         res = {}
-        for name, fact in [("exact", B.FACT_SVD), ("predictor", B.FACT_RSVD_MLP), ("previous_rank", B.FACT_RSVD_PREV)]:
+        for name, fact in [("exact", B.FACT_SVD), ("predictor", B.FACT_RSVD_MLP), ("previous_rank", B.FACT_RSVD_PREV),
+                           ("fixed_sketch", B.FACT_RSVD_FIXED)]:
             st = B.strategy(max_bond, tol, sweeps=sweeps, factorization=fact)
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -214,7 +215,7 @@ def learned_rank(args):
                          "steps": info["steps"]}
             print(f"  {name}: {dt:.2f} s, accepted {info['rsvd_accepted']}, fallbacks {info['rsvd_fallbacks']}",
                   file=sys.stderr, flush=True)
-        for name in ("predictor", "previous_rank"):
+        for name in ("predictor", "previous_rank", "fixed_sketch"):
             res[name]["speedup_vs_exact"] = res["exact"]["seconds"] / res[name]["seconds"]
             res[name]["rel_norm_diff_vs_exact"] = abs(res[name]["norm"] - res["exact"]["norm"]) / res["exact"]["norm"]
         return res

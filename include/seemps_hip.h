@@ -66,7 +66,10 @@ enum {
 enum {
     SMPS_FACT_SVD = 0,        /* exact one-sided Jacobi SVD */
     SMPS_FACT_RSVD_MLP = 1,   /* randomized SVD sized by the rank predictor, exact SVD as fallback */
-    SMPS_FACT_RSVD_PREV = 2   /* randomized SVD sized by the bond's previous kept rank, exact fallback */
+    SMPS_FACT_RSVD_PREV = 2,  /* randomized SVD sized by the bond's previous kept rank, exact fallback */
+    SMPS_FACT_RSVD_FIXED = 3  /* randomized SVD with the sketch sized by the bond cap alone (no rank
+                                 estimate: r = min(max_bond, m, n)), exact fallback; the baseline that
+                                 the two estimates are measured against */
 };
 /* Randomized factorization (single-problem path only): Gaussian range finder
    (Halko, Martinsson & Tropp 2011, Alg. 4.1 with oversampling 16) on a sketch
@@ -74,8 +77,9 @@ enum {
    orthonormalised by two Gram passes (k x k Jacobi eigenproblems), then the
    SVD of the projected matrix (Rayleigh-Ritz) through its k x k Gram matrix.  r is the predicted rank: ceil(exp(output)) of the rank predictor on
    the bond's previous spectrum (RSVD_MLP), or the bond's previous kept rank
-   (RSVD_PREV).  The step is exact when r >= min(max_bond, m, n) (a rank at the
-   cap cannot meet the tolerance) or k >= min(m, n).  The discarded weight
+   (RSVD_PREV); for those two the step is exact when r >= min(max_bond, m, n)
+   (a rank at the cap cannot meet the tolerance).  RSVD_FIXED takes
+   r = min(max_bond, m, n).  Every mode is exact when k >= min(m, n).  The discarded weight
    ||theta||^2 - sum_{j<r} s_j^2 is exact; the step is accepted when it is at
    most tol * ||theta||^2 (relative-norm rule) and r <= k - 8, else the exact
    SVD replaces it.  The first left-to-right pass is always exact (no previous

@@ -167,16 +167,21 @@ class SketchedSplit:
     factorization schedule.  The first left-to-right pass is exact.  Later
     steps predict the rank r_hat from the bond's previous split: the kept
     rank there (predictor None) or ceil(exp(predictor(features))) clipped to
-    [1, min(max_bond, m, n)].  r_hat at that cap, or a sketch k = r_hat + p
-    of at least min(m, n) rows, means the exact SVD.  kinds[step] records
+    [1, min(max_bond, m, n)]; r_hat at that cap means the exact SVD.  With
+    fixed=True there is no estimate: r_hat = min(max_bond, m, n).  A sketch
+    k = r_hat + p of at least min(m, n) rows means the exact SVD.  kinds[step] records
     0 / +k accepted / -k replaced by the exact SVD."""
 
-    def __init__(self, max_bond: int, tol: float, mode: int = REL_NORM2, predictor=None):
+    def __init__(self, max_bond: int, tol: float, mode: int = REL_NORM2, predictor=None, fixed: bool = False):
         self.max_bond, self.tol, self.mode, self.predictor = max_bond, tol, mode, predictor
+        self.fixed = fixed
         self.kinds = []
 
     def sketch_size(self, prev, nv, ln):
         lim = min(nv, ln, self.max_bond)
+        if self.fixed:  # no rank estimate: the sketch covers the cap
+            k = lim + OVERSAMPLE
+            return k if k < min(nv, ln) else 0
         spectrum, rank = prev
         if self.predictor is None:
             rhat = min(lim, rank)

@@ -21,7 +21,7 @@ F64, F32 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "bf16": PREC_BF16}
 TRUNC_REL_NORM2, TRUNC_REL_SV = 0, 1
-FACT_SVD, FACT_RSVD_MLP, FACT_RSVD_PREV = 0, 1, 2
+FACT_SVD, FACT_RSVD_MLP, FACT_RSVD_PREV, FACT_RSVD_FIXED = 0, 1, 2, 3
 MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
 
 # every symbol the header declares, in declaration order

@@ -121,7 +121,7 @@ static int check_strategy(smps_ctx* c, const smps_strategy* st) {
     if (st->precision < SMPS_PREC_FP64 || st->precision > SMPS_PREC_BF16)
         return fail(c, SMPS_EINVAL, "unknown precision");
     if (st->factorization != SMPS_FACT_SVD && st->factorization != SMPS_FACT_RSVD_MLP &&
-        st->factorization != SMPS_FACT_RSVD_PREV)
+        st->factorization != SMPS_FACT_RSVD_PREV && st->factorization != SMPS_FACT_RSVD_FIXED)
         return fail(c, SMPS_EINVAL, "unknown factorization");
     return SMPS_OK;
 }

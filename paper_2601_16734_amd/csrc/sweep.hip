@@ -545,6 +545,10 @@ struct Enq {
     // not meet the tolerance, or a sketch as large as the matrix).
     int sketch_size(int k, int nv, int ln) const {
         const int lim = std::min(std::min(nv, ln), st.max_bond);
+        if (p.fact == SMPS_FACT_RSVD_FIXED) {  // sized by the cap: randomized whenever the cap is below the size
+            const int ks = lim + RSVD_OVERSAMPLE;
+            return ks < std::min(nv, ln) ? ks : 0;
+        }
         int rhat;
         if (p.fact == SMPS_FACT_RSVD_PREV) {
             rhat = std::min(lim, prev_rank[k]);
@@ -762,13 +766,14 @@ struct Enq {
         // ---- sweeps (Sec. 2.5)
         int step = 0;
         const bool rs = p.fact != SMPS_FACT_SVD;
+        const bool predicts = rs && p.fact != SMPS_FACT_RSVD_FIXED;  // sizing needs a rank estimate
         if (!rec) fact_log.assign(std::max(1, p.steps), 0);
         sweeps_done = 0;
         for (int sw = 0; sw < S; ++sw) {
             // bond k was last factorized in the previous half-sweep, at step
             // (2 sw - 1)(L - 1) + (L - 2 - k)
             const bool rs_lr = rs && sw > 0;
-            if (rs_lr && !rec) CK(predict_ranks((2 * sw - 1) * (L - 1) + (L - 2), -1));
+            if (rs_lr && predicts && !rec) CK(predict_ranks((2 * sw - 1) * (L - 1) + (L - 2), -1));
             for (int k = 0; k + 1 < L; ++k) {  // left to right
                 tag(3 + 2 * sw, k);
                 double* theta = at<double>(p.o_theta);
@@ -801,7 +806,7 @@ struct Enq {
                 ++step;
             }
             // bond k was last factorized in this sweep's left-to-right pass, at step 2 sw (L - 1) + k
-            if (rs && !rec) CK(predict_ranks(2 * sw * (L - 1), 1));
+            if (predicts && !rec) CK(predict_ranks(2 * sw * (L - 1), 1));
             for (int k = L - 2; k >= 0; --k) {  // right to left
                 tag(4 + 2 * sw, L - 2 - k);
                 double* theta = at<double>(p.o_theta);

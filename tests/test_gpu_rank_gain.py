@@ -62,7 +62,8 @@ def test_trained_predictor_sizes_accepted_sketches(ctx):
     mpo, mps = decaying(0)
     ref = om.apply_simplify(mpo, mps, 64, 1e-10, sweeps=2)
     report = {}
-    for name, fact in [("exact", B.FACT_SVD), ("predictor", B.FACT_RSVD_MLP), ("previous_rank", B.FACT_RSVD_PREV)]:
+    for name, fact in [("exact", B.FACT_SVD), ("predictor", B.FACT_RSVD_MLP), ("previous_rank", B.FACT_RSVD_PREV),
+                       ("fixed_sketch", B.FACT_RSVD_FIXED)]:
         timed_apply(ctx, mpo, mps, 64, fact)  # first call sizes the workspace
         dt, got, info = timed_apply(ctx, mpo, mps, 64, fact)
         assert rel_norm_err(info["norm"], ref.norm) <= 1e-10, name

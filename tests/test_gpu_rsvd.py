@@ -39,15 +39,18 @@ def run(ctx, mps, mpo, max_bond, tol, sweeps, fact):
     return out.read(), ctx.last_info(), ctx.last_factor_log(), ctx.last_log()
 
 
-@pytest.mark.parametrize("fact", [B.FACT_RSVD_MLP, B.FACT_RSVD_PREV])
+@pytest.mark.parametrize("fact", [B.FACT_RSVD_MLP, B.FACT_RSVD_PREV, B.FACT_RSVD_FIXED])
 def test_randomized_schedule_matches_oracle(ctx, fact):
     mps, mpo = decaying_case(16, 64, (3.0, 6.0), 1)
     pred = constant_predictor(ctx, 24.5)
-    hook = orsvd.SketchedSplit(64, 1e-10, predictor=pred if fact == B.FACT_RSVD_MLP else None)
-    ref = om.apply_simplify(mpo, mps, 64, 1e-10, sweeps=2, split_hook=hook)
-    got, info, kinds, (deltas, ranks, _) = run(ctx, mps, mpo, 64, 1e-10, 2, fact)
+    # the cap-sized sketch needs a cap below the bulk matrix size (ranks stay ~25)
+    fixed = fact == B.FACT_RSVD_FIXED
+    cap, least = (32, 6) if fixed else (64, 10)
+    hook = orsvd.SketchedSplit(cap, 1e-10, predictor=pred if fact == B.FACT_RSVD_MLP else None, fixed=fixed)
+    ref = om.apply_simplify(mpo, mps, cap, 1e-10, sweeps=2, split_hook=hook)
+    got, info, kinds, (deltas, ranks, _) = run(ctx, mps, mpo, cap, 1e-10, 2, fact)
     assert list(kinds) == hook.kinds
-    assert info["rsvd_accepted"] == sum(k > 0 for k in hook.kinds) >= 10
+    assert info["rsvd_accepted"] == sum(k > 0 for k in hook.kinds) >= least
     assert info["rsvd_fallbacks"] == 0
     assert [1] + [t.shape[2] for t in got] == ref.ranks
     assert rel_norm_err(info["norm"], ref.norm) <= 1e-10
