@@ -14,9 +14,11 @@
 //
 // Workgroup: 256 threads = 4 wave64s arranged 2 x 2 over a TM x TN output
 // tile (TM, TN in {32, 64}); each wave owns a (TM/2) x (TN/2) block of
-// 16 x 16 MFMA outputs.  Small products (few tiles) run faster on the smaller
-// tiles, larger ones on 64 x 64; the tile of each product shape is chosen by
-// the autotuner (autotune.hip) when a table entry exists, else 64 x 64.
+// 16 x 16 MFMA outputs.  K is consumed in deep chunks whose global loads are
+// issued one chunk ahead, into registers.  Small products (few tiles) run
+// faster on the smaller tiles, larger ones on 64 x 64; the tile of each
+// product shape is chosen by the autotuner (autotune.hip) when a table entry
+// exists, else 64 x 64.
 
 #include "common.h"
 
@@ -27,15 +29,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 
-template <typename T>
-__device__ __forceinline__ double ldg(const void* p, size_t i) {
-    return (double)((const T*)p)[i];
-}
-template <typename T>
-__device__ __forceinline__ float ldgf(const void* p, size_t i) {
-    return (float)((const T*)p)[i];
-}
-
 __device__ __forceinline__ unsigned short f2bf(float x) {
     // round to nearest even (inputs are finite)
     unsigned u = __float_as_uint(x);
@@ -44,27 +37,32 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
-// Element (row r, col c) of the logical M x K operand A, or of the logical K x N operand B.
-template <typename T>
-__device__ __forceinline__ double opA(const void* A, int ta, int M, int K, int r, int k) {
-    return ta ? ldg<T>(A, (size_t)k * M + r) : ldg<T>(A, (size_t)r * K + k);
-}
+// ---------------------------------------------------------------------------
+// FP64 / FP32 path: LDS holds A as [k][m] and B as [k][n].  The K loop is
+// latency-bound at these sizes (a few to a few tens of workgroups, the next
+// chunk cannot start before its loads return), so chunks are deep (BK = 32
+// for 64 x 64 tiles, 64 otherwise) and the next chunk's global loads are
+// issued into registers before the current chunk's MFMAs.  The MFMA sequence
+// over k is k = 0, 4, 8, ... in every configuration; k steps beyond K are
+// skipped (they would add exact zeros).
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__host__ __device__ constexpr int gemm_bk_f() { return (BM == 64 && BN == 64) ? 32 : 64; }
 
-// ---------------------------------------------------------------------------
-// FP64 / FP32 path: BK = 16, LDS holds A as [k][m] and B as [k][n].
-// ---------------------------------------------------------------------------
 template <int PREC, typename TA, typename TB, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc* garr) {
     // one descriptor, or one per blockIdx.z (batched launch over independent problems)
     const GemmDesc g = garr ? garr[blockIdx.z] : g0;
     using CT = typename std::conditional<PREC == P_F64, double, float>::type;
-    constexpr int BK = 16;
+    constexpr int BK = gemm_bk_f<BM, BN>();
+    constexpr int NA = BM * BK / 256, NB = BN * BK / 256;  // elements per thread per chunk
     const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     if (m0 >= M || n0 >= N) return;
     const void* A = g.A;
     const void* B = g.B;
     void* C = g.C;
+    const int ta = g.ta, tb = g.tb;
 
     __shared__ CT As[BK][BM + 4];
     __shared__ CT Bs[BK][BN + 4];
@@ -79,31 +77,52 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
+    // element e of a chunk: (row, k) of A and (k, col) of B, coalesced along
+    // the operand's contiguous index
+    auto a_at = [&](int e, int& mm, int& kk) {
+        if (!ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+    };
+    auto b_at = [&](int e, int& nn, int& kk) {
+        if (!tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
+    };
+    TA ra[NA];
+    TB rb[NB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            int mm, kk;
+            a_at(i * 256 + tid, mm, kk);
+            const int gm = m0 + mm, gk = k0 + kk;
+            ra[i] = (gm < M && gk < K) ? (ta ? ((const TA*)A)[(size_t)gk * M + gm] : ((const TA*)A)[(size_t)gm * K + gk])
+                                       : (TA)0;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            int nn, kk;
+            b_at(i * 256 + tid, nn, kk);
+            const int gn = n0 + nn, gk = k0 + kk;
+            rb[i] = (gn < N && gk < K) ? (tb ? ((const TB*)B)[(size_t)gn * K + gk] : ((const TB*)B)[(size_t)gk * N + gn])
+                                       : (TB)0;
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int e0 = 0; e0 < BM * BK; e0 += 256) {
-            const int e = e0 + tid;
+        for (int i = 0; i < NA; ++i) {
             int mm, kk;
-            if (!g.ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            CT v = 0;
-            if (gm < M && gk < K) v = (CT)opA<TA>(A, g.ta, M, K, gm, gk);
-            As[kk][mm] = v;
+            a_at(i * 256 + tid, mm, kk);
+            As[kk][mm] = (CT)ra[i];
         }
 #pragma unroll
-        for (int e0 = 0; e0 < BN * BK; e0 += 256) {
-            const int e = e0 + tid;
+        for (int i = 0; i < NB; ++i) {
             int nn, kk;
-            if (!g.tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
-            const int gn = n0 + nn, gk = k0 + kk;
-            CT v = 0;
-            if (gn < N && gk < K)
-                v = (CT)(g.tb ? ldg<TB>(B, (size_t)gn * K + gk) : ldg<TB>(B, (size_t)gk * N + gn));
-            Bs[kk][nn] = v;
+            b_at(i * 256 + tid, nn, kk);
+            Bs[kk][nn] = (CT)rb[i];
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
+        if (k0 + BK < K) fetch(k0 + BK);  // in flight during this chunk's MFMAs
+        const int kend = min(BK, K - k0);
+        for (int kk = 0; kk < kend; kk += 4) {
             CT a[FM], b[FN];
             for (int i = 0; i < FM; ++i) a[i] = As[kk + lk][wm + i * 16 + li];
             for (int j = 0; j < FN; ++j) b[j] = Bs[kk + lk][wn + j * 16 + li];
@@ -136,14 +155,17 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
 }
 
 // ---------------------------------------------------------------------------
-// BF16 / BF16x3 path: BK = 32, LDS holds A as [m][k] and B as [n][k] so that a
-// lane's eight consecutive k values are one 16-byte read.
+// BF16 / BF16x3 path: LDS holds A as [m][k] and B as [n][k] so that a lane's
+// eight consecutive k values are one 16-byte read.  Chunks of BK = 64 (two
+// MFMA k steps of 32), the next chunk's loads issued before this chunk's
+// MFMAs; operands are rounded (and split) while being stored to LDS.
 // ---------------------------------------------------------------------------
 template <int PREC, typename TA, typename TB, typename TC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDesc* garr) {
     // one descriptor, or one per blockIdx.z (batched launch over independent problems)
     const GemmDesc g = garr ? garr[blockIdx.z] : g0;
-    constexpr int BK = 32, LD = BK + 8;
+    constexpr int BK = 64, LD = BK + 8;
+    constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
     constexpr bool SPLIT = (PREC == P_BF16X3);
     const int M = eval_dim(g.dims, g.M), N = eval_dim(g.dims, g.N), K = eval_dim(g.dims, g.K);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
@@ -151,6 +173,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
     const void* A = g.A;
     const void* B = g.B;
     void* C = g.C;
+    const int ta = g.ta, tb = g.tb;
 
     __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LD];
     __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LD];
@@ -166,50 +189,76 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.f;
 
+    auto a_at = [&](int e, int& mm, int& kk) {
+        if (!ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+    };
+    auto b_at = [&](int e, int& nn, int& kk) {
+        if (!tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
+    };
+    TA ra[NA];
+    TB rb[NB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            int mm, kk;
+            a_at(i * 256 + tid, mm, kk);
+            const int gm = m0 + mm, gk = k0 + kk;
+            ra[i] = (gm < M && gk < K) ? (ta ? ((const TA*)A)[(size_t)gk * M + gm] : ((const TA*)A)[(size_t)gm * K + gk])
+                                       : (TA)0;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            int nn, kk;
+            b_at(i * 256 + tid, nn, kk);
+            const int gn = n0 + nn, gk = k0 + kk;
+            rb[i] = (gn < N && gk < K) ? (tb ? ((const TB*)B)[(size_t)gn * K + gk] : ((const TB*)B)[(size_t)gk * N + gn])
+                                       : (TB)0;
+        }
+    };
+    fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int e0 = 0; e0 < BM * BK; e0 += 256) {
-            const int e = e0 + tid;
+        for (int i = 0; i < NA; ++i) {
             int mm, kk;
-            if (!g.ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-            const int gm = m0 + mm, gk = k0 + kk;
-            float v = 0.f;
-            if (gm < M && gk < K) v = (float)opA<TA>(A, g.ta, M, K, gm, gk);
+            a_at(i * 256 + tid, mm, kk);
+            const float v = (float)ra[i];
             const unsigned short h = f2bf(v);
             Ah[mm][kk] = h;
             if constexpr (SPLIT) Al[mm][kk] = f2bf(v - bf2f(h));
         }
 #pragma unroll
-        for (int e0 = 0; e0 < BN * BK; e0 += 256) {
-            const int e = e0 + tid;
+        for (int i = 0; i < NB; ++i) {
             int nn, kk;
-            if (!g.tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
-            const int gn = n0 + nn, gk = k0 + kk;
-            float v = 0.f;
-            if (gn < N && gk < K)
-                v = (float)(g.tb ? ldg<TB>(B, (size_t)gn * K + gk) : ldg<TB>(B, (size_t)gk * N + gn));
+            b_at(i * 256 + tid, nn, kk);
+            const float v = (float)rb[i];
             const unsigned short h = f2bf(v);
             Bh[nn][kk] = h;
             if constexpr (SPLIT) Bl[nn][kk] = f2bf(v - bf2f(h));
         }
         __syncthreads();
-        v8bf ah[FM], bh[FN], al[FM], bl[FN];
-        for (int i = 0; i < FM; ++i) {
-            ah[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Ah[wm + i * 16 + li][lk * 8]);
-            if constexpr (SPLIT) al[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Al[wm + i * 16 + li][lk * 8]);
-        }
-        for (int j = 0; j < FN; ++j) {
-            bh[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bh[wn + j * 16 + li][lk * 8]);
-            if constexpr (SPLIT) bl[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bl[wn + j * 16 + li][lk * 8]);
-        }
-        for (int i = 0; i < FM; ++i)
-            for (int j = 0; j < FN; ++j) {
-                if constexpr (SPLIT) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                }
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        if (k0 + BK < K) fetch(k0 + BK);  // in flight during this chunk's MFMAs
+        const int kend = min(BK, K - k0);
+        for (int ks = 0; ks < kend; ks += 32) {
+            v8bf ah[FM], bh[FN], al[FM], bl[FN];
+            for (int i = 0; i < FM; ++i) {
+                ah[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Ah[wm + i * 16 + li][ks + lk * 8]);
+                if constexpr (SPLIT)
+                    al[i] = __builtin_bit_cast(v8bf, *(const uint4*)&Al[wm + i * 16 + li][ks + lk * 8]);
             }
+            for (int j = 0; j < FN; ++j) {
+                bh[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bh[wn + j * 16 + li][ks + lk * 8]);
+                if constexpr (SPLIT)
+                    bl[j] = __builtin_bit_cast(v8bf, *(const uint4*)&Bl[wn + j * 16 + li][ks + lk * 8]);
+            }
+            for (int i = 0; i < FM; ++i)
+                for (int j = 0; j < FN; ++j) {
+                    if constexpr (SPLIT) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
         __syncthreads();
     }
     const float alpha = (float)g.alpha;
