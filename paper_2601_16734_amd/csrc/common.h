@@ -102,6 +102,16 @@ struct JacobiDesc {
                          // start) with the vectors; Q then receives the rows of J of the kept
                          // values (the singular vectors on the nvec side, r x nvec) and basis,
                          // when given, the whole J (nvec x nvec)
+    // Warm start of an accumulated factorization (nullable acc_tag: none).  acc_basis is the
+    // nvec x nvec J that the last accumulated factorization at this bond in the same
+    // orientation left, valid when *acc_tag == 2 nvec + acc_dir + 1.  Valid: X holds
+    // acc_basis times the raw vectors and J starts from acc_basis; otherwise the raw
+    // vectors are read from X_raw and J starts from the identity.  The final J is saved
+    // back to acc_basis with its tag.
+    const double* X_raw;
+    double* acc_basis;
+    int* acc_tag;
+    int acc_dir;
 };
 
 }  // namespace smps

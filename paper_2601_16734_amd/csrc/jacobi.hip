@@ -533,10 +533,13 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     double* sig_sorted = sig_raw + nv;
     int* perm = (int*)(sig_sorted + nv);
     if (tid == 0) s_bad = 0;
+    // warm start of an accumulated factorization: X = J0 (raw vectors), J = J0
+    // (X == X_raw: the vectors were not pre-rotated, so J starts from the identity)
+    const bool warm = ACC && d.acc_tag && d.X != d.X_raw && *d.acc_tag == 2 * nv + d.acc_dir + 1;
     if (Jw)
-        for (int e = tid; e < nv * nv; e += LDS_NT) Jw[e] = (e / nv == e % nv) ? 1.0 : 0.0;
+        for (int e = tid; e < nv * nv; e += LDS_NT) Jw[e] = warm ? d.acc_basis[e] : (e / nv == e % nv) ? 1.0 : 0.0;
     __syncthreads();
-    const double* X = d.X;
+    const double* X = (ACC && d.acc_tag && !warm) ? d.X_raw : d.X;
     const int bad = load_rows_to_lds(W, nv, len, ld, [=](int j) { return X + (size_t)j * len; }, tid, LDS_NT);
     if (bad) s_bad = 1;
     __syncthreads();
@@ -569,6 +572,10 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
     jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram, Jw);
+    if (ACC && d.acc_tag) {
+        for (int e = tid; e < nv * nv; e += LDS_NT) d.acc_basis[e] = Jw[e];
+        if (tid == 0) *d.acc_tag = 2 * nv + d.acc_dir + 1;
+    }
 }
 
 // Threads of a blocked-path workgroup: G = 16 as the LDS kernel of class E;

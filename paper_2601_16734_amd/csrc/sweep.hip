@@ -61,6 +61,8 @@ struct Plan {
     // offsets into the workspace
     size_t o_dims, o_status, o_flag, o_done, o_norm2, o_fro2;
     std::vector<size_t> o_psi, o_L, o_R, o_XL, o_XR, o_basis;
+    std::vector<size_t> o_accJ;  // per bond: J of the last accumulated factorization there
+    size_t o_acctag = 0;         // per bond: validity tag of o_accJ (2 nvec + direction + 1)
     size_t o_tmp, o_theta, o_theta2, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
     size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
     size_t o_R64a, o_R64b, o_XR64, o_Y64;
@@ -169,6 +171,13 @@ void plan_problem(Plan& p, const smps_mpo* U, const smps_mps* v, const smps_stra
         const size_t nb = std::max((size_t)c[k] * e[k], (size_t)e[k + 1] * c[k + 2]);
         p.o_basis[k] = lay.add(8 * nb * nb);
     }
+    // accumulated factorizations run on the shorter side and in LDS only
+    p.o_accJ.assign(std::max(1, L - 1), 0);
+    for (int k = 0; k + 1 < L; ++k) {
+        const int lo = std::min(c[k] * e[k], e[k + 1] * c[k + 2]), hi = std::max(c[k] * e[k], e[k + 1] * c[k + 2]);
+        if (lo < hi && jacobi_fits_lds(lo, hi, true)) p.o_accJ[k] = lay.add(8 * (size_t)lo * lo);
+    }
+    p.o_acctag = lay.add(sizeof(int) * std::max(1, L - 1));
     p.o_Q = lay.add(8 * p.max_theta);
     p.o_carry = lay.add(8 * p.max_theta);
     p.o_tmpB = lay.add(8 * p.max_theta);
@@ -638,7 +647,7 @@ struct Enq {
     // randomized: this bond was factorized before in this call and a
     // randomized method is requested.
     hipError_t factor(int k, int step, bool rotate, bool randomized, double* theta, DimExpr nvec, DimExpr len,
-                      int nvec_cap, int len_cap, double* dest, int mr, bool acc = false) const {
+                      int nvec_cap, int len_cap, double* dest, int mr, bool acc = false, int dir = 0) const {
         if (randomized && !rec) {
             hipError_t e = read_dims();
             if (e != hipSuccess) return e;
@@ -653,10 +662,14 @@ struct Enq {
             }
         }
         double* X = theta;
+        // an accumulated step pre-rotates by the J its last visit in the same
+        // direction left (the kernel falls back to theta when that J's tag does
+        // not match); any other step by the bond's basis
+        const bool acc_warm = acc && p.o_accJ[k] != 0;
         if (rotate) {
             X = at<double>(p.o_theta2);
-            hipError_t e = gemm(at(p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, nvec, len, nvec, 0, 0, 0, nvec_cap,
-                                len_cap, P_F64);
+            hipError_t e = gemm(at(acc_warm ? p.o_accJ[k] : p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, nvec, len,
+                                nvec, 0, 0, 0, nvec_cap, len_cap, P_F64);
             if (e != hipSuccess) return e;
         } else {
             ++cur_slot;  // the same slot numbering whether or not this step pre-rotates
@@ -664,6 +677,12 @@ struct Enq {
         JacobiDesc d = jac(X, dest, nvec, len, k + 1, mr, st.tol, st.trunc_mode, step);
         d.basis = at<double>(p.o_basis[k]);
         d.accumulate = acc;
+        if (acc_warm) {
+            d.X_raw = theta;
+            d.acc_basis = at<double>(p.o_accJ[k]);
+            d.acc_tag = at<int>(p.o_acctag) + k;
+            d.acc_dir = dir;
+        }
         return jacobi(d, nvec_cap, len_cap);
     }
 
@@ -709,6 +728,13 @@ struct Enq {
             op.kind = OP_SETINTS;
             op.set_base = at<int>(p.o_status);
             op.set_vals.assign(1, 0);
+            CK(emit(std::move(op)));
+        }
+        {  // no accumulated factorization has left a J yet
+            Op op;
+            op.kind = OP_SETINTS;
+            op.set_base = at<int>(p.o_acctag);
+            op.set_vals.assign(std::max(1, L - 1), 0);
             CK(emit(std::move(op)));
         }
         const int NT = nterms();
@@ -792,8 +818,8 @@ struct Enq {
                 // warm start (sw > 0): rotate by the right singular basis this bond
                 // produced in the previous right-to-left pass (identity when it was not full)
                 if (acc)
-                    CK(factor(k, step, false, rs_lr, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
-                              e[k + 1] * c[k + 2], at<double>(p.o_Q), mr, true));
+                    CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
+                              e[k + 1] * c[k + 2], at<double>(p.o_Q), mr, true, 0));
                 else
                     CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]),
                               e[k + 1] * c[k + 2], c[k] * e[k], at<double>(p.o_Q), mr));
@@ -823,8 +849,8 @@ struct Enq {
                 const int mr = std::min(st.max_bond, c[k + 1]);
                 // warm start from the left singular basis of this pass's left-to-right visit
                 if (acc)
-                    CK(factor(k, step, false, rs, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
-                              c[k] * e[k], at<double>(p.o_psi[k + 1]), mr, true));
+                    CK(factor(k, step, sw > 0, rs, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
+                              c[k] * e[k], at<double>(p.o_psi[k + 1]), mr, true, 1));
                 else
                     CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
                               e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
