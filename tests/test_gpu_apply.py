@@ -126,6 +126,28 @@ def test_random_mpo_n20_chi64_fp64(ctx, c2_oracle):
     assert info["steps"] == 4 * 2 * 19
 
 
+def test_accumulated_edge_steps_warm_start_from_their_last_visit(ctx, c2_oracle):
+    """n=20 chi=64 D=8, 4 sweeps: the first six steps of every pass (bond
+    dimensions growing from the chain's end) factorize the shorter side with
+    accumulated rotations, each starting from the J that the same step of the
+    previous pass in that direction left.  Their rotating Jacobi sweeps in the
+    last pass of each direction stay well below the first pass of that
+    direction (started from the identity they would stay within ~10% of it),
+    and the result keeps FP64 parity with the oracle."""
+    w, ref = c2_oracle
+    got, err, info, _ = run_gpu(ctx, w)
+    assert rel_norm_err(info["norm"], ref.norm) <= 1e-12
+    assert cross_fidelity_loss(got, ref.mps) <= 1e-12
+    js = ctx.last_jacobi_log()
+    n = len(w.mps) - 1  # steps per pass
+    passes = 2 * w.sweeps
+    assert len(js) == passes * n
+    lead = [sum(js[p * n:p * n + 6]) for p in range(passes)]
+    print("rotating sweeps of the six leading steps per pass:", lead)
+    assert lead[passes - 2] <= 0.8 * lead[0]  # left-to-right passes
+    assert lead[passes - 1] <= 0.8 * lead[1]  # right-to-left passes
+
+
 @pytest.mark.parametrize("precision,bar", [("fp32", 1e-8), ("bf16x3", 1e-8), ("bf16", None)])
 def test_random_mpo_n20_chi64_mixed(ctx, c2_oracle, precision, bar):
     w, ref = c2_oracle
