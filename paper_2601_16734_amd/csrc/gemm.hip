@@ -37,6 +37,22 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
+// Staging geometry.  Element i (of a chunk) of thread tid sits at
+// (outer0 + i d_outer, inner0 + i d_inner) of the operand tile, lanes running
+// along the operand's contiguous index: A (M x K row-major) rows tid / BK +
+// i 256 / BK at k = tid % BK; A^T (K x M row-major) k = tid / BM + i 256 / BM at
+// m = tid % BM; B likewise with BN.  So every element is one base address plus
+// a constant stride, in global memory and in LDS.
+struct StageAxis {
+    int mn0, k0, dmn, dk;  // tile coordinates of element 0 and per-element steps
+};
+template <int BMN, int BK>
+__device__ __forceinline__ StageAxis stage_axis(int tid, bool k_contiguous) {
+    static_assert(256 % BK == 0 && 256 % BMN == 0, "staging needs tile sides dividing 256");
+    if (k_contiguous) return StageAxis{tid / BK, tid % BK, 256 / BK, 0};
+    return StageAxis{tid % BMN, tid / BMN, 0, 256 / BMN};
+}
+
 // ---------------------------------------------------------------------------
 // FP64 / FP32 path: LDS holds A as [k][m] and B as [k][n].  The K loop is
 // latency-bound at these sizes (a few to a few tens of workgroups, the next
@@ -77,48 +93,34 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
 
-    // element e of a chunk: (row, k) of A and (k, col) of B, coalesced along
-    // the operand's contiguous index
-    auto a_at = [&](int e, int& mm, int& kk) {
-        if (!ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-    };
-    auto b_at = [&](int e, int& nn, int& kk) {
-        if (!tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
-    };
+    // operand tiles: A as (m, k) with k contiguous unless transposed, B as
+    // (n, k) with n contiguous unless transposed
+    const StageAxis sa = stage_axis<BM, BK>(tid, !ta), sb = stage_axis<BN, BK>(tid, tb);
+    const size_t a_step = ta ? (size_t)sa.dk * M : (size_t)sa.dmn * K;
+    const size_t b_step = tb ? (size_t)sb.dmn * K : (size_t)sb.dk * N;
+    CT* const as0 = &As[sa.k0][sa.mn0];
+    CT* const bs0 = &Bs[sb.k0][sb.mn0];
+    const int as_step = sa.dk * (BM + 4) + sa.dmn, bs_step = sb.dk * (BN + 4) + sb.dmn;
     TA ra[NA];
     TB rb[NB];
     auto fetch = [&](int k0) {
+        const int gm0 = m0 + sa.mn0, ga0 = k0 + sa.k0;
+        const TA* pa = (const TA*)A + (ta ? (size_t)ga0 * M + gm0 : (size_t)gm0 * K + ga0);
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            int mm, kk;
-            a_at(i * 256 + tid, mm, kk);
-            const int gm = m0 + mm, gk = k0 + kk;
-            ra[i] = (gm < M && gk < K) ? (ta ? ((const TA*)A)[(size_t)gk * M + gm] : ((const TA*)A)[(size_t)gm * K + gk])
-                                       : (TA)0;
-        }
+        for (int i = 0; i < NA; ++i)
+            ra[i] = (gm0 + i * sa.dmn < M && ga0 + i * sa.dk < K) ? pa[i * a_step] : (TA)0;
+        const int gn0 = n0 + sb.mn0, gb0 = k0 + sb.k0;
+        const TB* pb = (const TB*)B + (tb ? (size_t)gn0 * K + gb0 : (size_t)gb0 * N + gn0);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            int nn, kk;
-            b_at(i * 256 + tid, nn, kk);
-            const int gn = n0 + nn, gk = k0 + kk;
-            rb[i] = (gn < N && gk < K) ? (tb ? ((const TB*)B)[(size_t)gn * K + gk] : ((const TB*)B)[(size_t)gk * N + gn])
-                                       : (TB)0;
-        }
+        for (int i = 0; i < NB; ++i)
+            rb[i] = (gn0 + i * sb.dmn < N && gb0 + i * sb.dk < K) ? pb[i * b_step] : (TB)0;
     };
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            int mm, kk;
-            a_at(i * 256 + tid, mm, kk);
-            As[kk][mm] = (CT)ra[i];
-        }
+        for (int i = 0; i < NA; ++i) as0[i * as_step] = (CT)ra[i];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            int nn, kk;
-            b_at(i * 256 + tid, nn, kk);
-            Bs[kk][nn] = (CT)rb[i];
-        }
+        for (int i = 0; i < NB; ++i) bs0[i * bs_step] = (CT)rb[i];
         __syncthreads();
         if (k0 + BK < K) fetch(k0 + BK);  // in flight during this chunk's MFMAs
         const int kend = min(BK, K - k0);
@@ -189,51 +191,40 @@ __global__ __launch_bounds__(256) void gemm_kernel_bf(GemmDesc g0, const GemmDes
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.f;
 
-    auto a_at = [&](int e, int& mm, int& kk) {
-        if (!ta) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
-    };
-    auto b_at = [&](int e, int& nn, int& kk) {
-        if (!tb) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
-    };
+    const StageAxis sa = stage_axis<BM, BK>(tid, !ta), sb = stage_axis<BN, BK>(tid, tb);
+    const size_t a_step = ta ? (size_t)sa.dk * M : (size_t)sa.dmn * K;
+    const size_t b_step = tb ? (size_t)sb.dmn * K : (size_t)sb.dk * N;
+    const int a_off = sa.mn0 * LD + sa.k0, as_step = sa.dmn * LD + sa.dk;
+    const int b_off = sb.mn0 * LD + sb.k0, bs_step = sb.dmn * LD + sb.dk;
     TA ra[NA];
     TB rb[NB];
     auto fetch = [&](int k0) {
+        const int gm0 = m0 + sa.mn0, ga0 = k0 + sa.k0;
+        const TA* pa = (const TA*)A + (ta ? (size_t)ga0 * M + gm0 : (size_t)gm0 * K + ga0);
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            int mm, kk;
-            a_at(i * 256 + tid, mm, kk);
-            const int gm = m0 + mm, gk = k0 + kk;
-            ra[i] = (gm < M && gk < K) ? (ta ? ((const TA*)A)[(size_t)gk * M + gm] : ((const TA*)A)[(size_t)gm * K + gk])
-                                       : (TA)0;
-        }
+        for (int i = 0; i < NA; ++i)
+            ra[i] = (gm0 + i * sa.dmn < M && ga0 + i * sa.dk < K) ? pa[i * a_step] : (TA)0;
+        const int gn0 = n0 + sb.mn0, gb0 = k0 + sb.k0;
+        const TB* pb = (const TB*)B + (tb ? (size_t)gn0 * K + gb0 : (size_t)gb0 * N + gn0);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            int nn, kk;
-            b_at(i * 256 + tid, nn, kk);
-            const int gn = n0 + nn, gk = k0 + kk;
-            rb[i] = (gn < N && gk < K) ? (tb ? ((const TB*)B)[(size_t)gn * K + gk] : ((const TB*)B)[(size_t)gk * N + gn])
-                                       : (TB)0;
-        }
+        for (int i = 0; i < NB; ++i)
+            rb[i] = (gn0 + i * sb.dmn < N && gb0 + i * sb.dk < K) ? pb[i * b_step] : (TB)0;
     };
     fetch(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
-            int mm, kk;
-            a_at(i * 256 + tid, mm, kk);
             const float v = (float)ra[i];
             const unsigned short h = f2bf(v);
-            Ah[mm][kk] = h;
-            if constexpr (SPLIT) Al[mm][kk] = f2bf(v - bf2f(h));
+            (&Ah[0][0])[a_off + i * as_step] = h;
+            if constexpr (SPLIT) (&Al[0][0])[a_off + i * as_step] = f2bf(v - bf2f(h));
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            int nn, kk;
-            b_at(i * 256 + tid, nn, kk);
             const float v = (float)rb[i];
             const unsigned short h = f2bf(v);
-            Bh[nn][kk] = h;
-            if constexpr (SPLIT) Bl[nn][kk] = f2bf(v - bf2f(h));
+            (&Bh[0][0])[b_off + i * bs_step] = h;
+            if constexpr (SPLIT) (&Bl[0][0])[b_off + i * bs_step] = f2bf(v - bf2f(h));
         }
         __syncthreads();
         if (k0 + BK < K) fetch(k0 + BK);  // in flight during this chunk's MFMAs
