@@ -80,8 +80,8 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
     void* C = g.C;
     const int ta = g.ta, tb = g.tb;
 
-    __shared__ CT As[BK][BM + 4];
-    __shared__ CT Bs[BK][BN + 4];
+    __shared__ CT As[BK][BM + 1];
+    __shared__ CT Bs[BK][BN + 1];
     constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 fragments per wave
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void gemm_kernel_f(GemmDesc g0, const GemmDesc
     const size_t b_step = tb ? (size_t)sb.dmn * K : (size_t)sb.dk * N;
     CT* const as0 = &As[sa.k0][sa.mn0];
     CT* const bs0 = &Bs[sb.k0][sb.mn0];
-    const int as_step = sa.dk * (BM + 4) + sa.dmn, bs_step = sb.dk * (BN + 4) + sb.dmn;
+    const int as_step = sa.dk * (BM + 1) + sa.dmn, bs_step = sb.dk * (BN + 1) + sb.dmn;
     TA ra[NA];
     TB rb[NB];
     auto fetch = [&](int k0) {
