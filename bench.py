@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--complex", action="store_true",
                     help="only measure the complex apply + compression (random complex MPO D=4 on a random complex "
                          "MPS n=20 chi=32, max bond 32, tol 1e-10, 4 sweeps) and print its JSON line")
+    ap.add_argument("--c3-applies", type=int, default=3,
+                    help="timed applies per precision of the L=100 chi=256 sub-record of the default run "
+                         "(after one warm-up); 0 skips it")
     ap.add_argument("--large", action="store_true",
                     help="only measure the L=100 chi=256 XXZ workload (4 sweeps, FP64 and mixed contractions, the "
                          "whole oracle as parity reference; several minutes) and print its JSON line")
@@ -146,14 +149,21 @@ def time_oracle(fn, budget_s: float):
     return best, {"s_per_call_all_threads": many, "threads_all": int(all_threads), "s_per_call_1_thread": one}
 
 
-def measured_traffic(path: str, source: str):
+def source_sha256(sources) -> str:
+    """sha256 over the concatenated kernel sources (one path or a list)."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in ([sources] if isinstance(sources, str) else sources):
+        h.update(open(src, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(path: str, sources):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source (None otherwise)."""
-    import hashlib
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith(" "))
-        sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256", "").strip() != sha:
+        if kv.get("kernel_source_sha256", "").strip() != source_sha256(sources):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -775,6 +785,70 @@ def replicas_leg(args):
     ctx.close()
 
 
+def c3_subrecord(ctx, args, stream):
+    """The L=100 d=2 chi=256 chain under the XXZ-type MPO D=5 (couplings
+    U[0.5,1.5]), max bond 256, tol 1e-10, 4 sweeps: one warm-up and
+    args.c3_applies timed applies per precision (inputs resident in HBM, no
+    profiling inside the timed region), each timed result checked against the
+    oracle's whole run stored in tests/golden (written by the oracle alone):
+    kept ranks of all 792 steps, the final norm (1e-8 bar) and three probe
+    overlaps."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    with open(os.path.join(ROOT, "tests", "golden", "xxz_L100_chi256_s4.json")) as fh:
+        g = json.load(fh)
+    w = synth.workload_xxz(0)
+    L, sweeps = len(w.mps), g["sweeps"]
+    su = sweeps * 2 * (L - 1)
+    # the probe states of the stored run (seed stream 90), overlaps taken on the device
+    probes = [ctx.mps_create(synth.random_mps(synth.rng_for(90, i), L, 2, 8)) for i in range(3)]
+    v = ctx.mps_create_device([torch.from_numpy(t).to("cuda") for t in w.mps])
+    U = ctx.mpo_create(w.mpo)
+    torch.cuda.synchronize()
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        st = B.strategy(w.max_bond, w.tol, sweeps=sweeps, precision=prec)
+        o, _ = ctx.mpo_apply(U, v, st)  # warm-up (graph captures of the blocked split)
+        o.destroy()
+        torch.cuda.synchronize()
+        times, checks = [], []
+        for _ in range(max(1, args.c3_applies)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out, err = ctx.mpo_apply(U, v, st)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+            _, ranks, _ = ctx.last_log()
+            nrm = ctx.last_info()["norm"]
+            pr = max(abs(ctx.scprod(p, out) - r) / abs(r) for p, r in zip(probes, g["probe_overlaps"]))
+            checks.append((abs(nrm - g["norm"]) / g["norm"], list(ranks) == g["step_ranks"], pr))
+            out.destroy()
+        ms = float(np.median(times))
+        rel = max(c[0] for c in checks)
+        res[prec] = {"ms_per_apply_median": ms, "ms_per_apply_all": times, "site_updates_per_s": su / (ms * 1e-3),
+                     "rel_norm_err_vs_oracle": rel, "step_ranks_equal_oracle": all(c[1] for c in checks),
+                     "probe_overlap_rel_err": max(c[2] for c in checks),
+                     "parity_1e-8": bool(rel <= 1e-8 and all(c[1] for c in checks))}
+        print(f"c3 sub-record: {prec} {su / (ms * 1e-3):.1f} site-updates/s, norm err {rel:.1e}", file=sys.stderr,
+              flush=True)
+    for h in probes + [v, U]:
+        h.destroy()
+    fp64 = res["fp64"]["site_updates_per_s"]
+    ok = [p for p in ("fp32", "bf16x3") if res[p]["parity_1e-8"]]
+    best = max(ok, key=lambda p: res[p]["site_updates_per_s"]) if ok else None
+    return {"workload": "XXZ-type MPO D=5 (couplings U[0.5,1.5]) on random MPS L=100 d=2 chi=256, max bond 256, "
+                        f"tol 1e-10, {sweeps} sweeps", "site_updates_per_apply": su, "warmup": 1,
+            "applies": max(1, args.c3_applies), "parity_reference": "oracle whole run, tests/golden",
+            "per_precision": res, "best_mixed": best,
+            "speedup_vs_fp64": (res[best]["site_updates_per_s"] / fp64) if best else None,
+            "oracle_cpu_seconds": g.get("oracle_seconds")}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -859,7 +933,7 @@ def main():
             out, _ = ctx.mpo_apply(U, v, st)
             out.destroy()
         torch.cuda.synchronize()
-        ctx.set_profiling(True)
+        # timed region: no per-launch profiling events
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
         outs = []
@@ -873,16 +947,25 @@ def main():
         ms = start.elapsed_time(stop) / args.steps
         per = np.array([start.elapsed_time(marks[0])] +
                        [marks[i - 1].elapsed_time(marks[i]) for i in range(1, args.steps)])
-        fact_ms, fact_n = ctx.kernel_time(0)
-        ctx.set_profiling(False)
         info = ctx.last_info()
-        contr_ms = max(1e-9, ms - fact_ms / args.steps)
+        # separate pass (one apply) for the factorization split: HIP events on
+        # the context stream around every split launch (category 0) and around
+        # the bulk 128 x 128 splits (category 2)
+        ctx.set_profiling(True)
+        prof_out, _ = ctx.mpo_apply(U, v, st)
+        fact_ms, fact_n = ctx.kernel_time(0)
+        bulk_ms, bulk_n = ctx.kernel_time(2)
+        ctx.set_profiling(False)
+        prof_out.destroy()
+        contr_ms = max(1e-9, ms - fact_ms)
         peak, issue = MFMA_PEAK.get(prec, (78.6, 1))
         rec = {"ms_per_step": ms, "site_updates_per_s": site_updates / (ms / 1e3),
                "step_ms_median": float(np.median(per)),
                "step_ms_iqr": float(np.percentile(per, 75) - np.percentile(per, 25)),
-               "factorization_ms_per_step": fact_ms / args.steps,
-               "factorization_launches_per_step": fact_n / args.steps, "norm": info["norm"],
+               "factorization_ms_per_step": fact_ms,
+               "factorization_launches_per_step": fact_n,
+               "bulk_split_ms_avg": bulk_ms / max(1, bulk_n), "bulk_splits_per_step": bulk_n,
+               "norm": info["norm"],
                "contraction_tflops": cflops / (contr_ms * 1e-3) / 1e12,
                "contraction_mfma_frac": issue * cflops / (contr_ms * 1e-3) / 1e12 / peak}
         if ref is not None:
@@ -901,18 +984,25 @@ def main():
     best_p = max(mixed, key=lambda p: mixed[p]["site_updates_per_s"]) if mixed else "fp64"
     best = results[best_p]
 
-    # roofline of the dominant kernel (the FP64 one-sided Jacobi factorization)
+    # roofline of the dominant kernel: the FP64 one-sided Jacobi split of the
+    # bulk 128 x 128 two-site tensor (jacobi_lds_kernel<8, false>), charged the
+    # full-SVD count 20 (d chi)^3 per launch, over its average launch time
+    # (HIP events on the context stream in the profiled pass)
     f = results[best_p]
-    fact_avg_ms = f["factorization_ms_per_step"] / max(1e-9, f["factorization_launches_per_step"])
-    flops_per_launch = flops_per_apply / max(1e-9, f["factorization_launches_per_step"])
-    achieved = flops_per_launch / (fact_avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "jacobi_lds_kernel<E> (FP64 one-sided Jacobi SVD, one workgroup per factorization)",
+    n_bulk = 2 * w.max_bond
+    bulk_flops = 20.0 * n_bulk ** 3
+    achieved = bulk_flops / (f["bulk_split_ms_avg"] * 1e-3) / 1e12
+    roofline = {"kernel": "jacobi_lds_kernel<8, false> (FP64 one-sided Jacobi SVD of the 128 x 128 bulk two-site "
+                          "tensor, one workgroup per split)",
                 "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic(os.path.join(ROOT, "profiles", "jacobi_lds_c2_traffic.txt"),
-                                            os.path.join(ROOT, "paper_2601_16734_amd", "csrc", "jacobi.hip")),
-                "avg_launch_ms": fact_avg_ms, "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"],
-                # context: a factorization is one workgroup, so it can use one of the 256 CUs
+                "traffic": measured_traffic(os.path.join(ROOT, "profiles", "jacobi_lds_bulk_n20_chi64_traffic.txt"),
+                                            [os.path.join(ROOT, "paper_2601_16734_amd", "csrc", x)
+                                             for x in ("jacobi.hip", "select.h")]),
+                "flops_per_launch": bulk_flops, "avg_launch_ms": f["bulk_split_ms_avg"],
+                "launches_per_step": f["bulk_splits_per_step"],
+                "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"],
+                # context: a split is one workgroup, so it can use one of the 256 CUs
                 "one_cu_peak": FP64_VECTOR_PEAK_TFLOPS / 256, "one_cu_frac": achieved / (FP64_VECTOR_PEAK_TFLOPS / 256)}
 
     line = {
@@ -937,6 +1027,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if args.c3_applies > 0:
+        line["c3_xxz_L100_chi256"] = c3_subrecord(ctx, args, stream)
     print(json.dumps(line))
     ctx.close()
 

@@ -122,8 +122,23 @@ int smps_ctx_destroy(smps_ctx *ctx);
 const char *smps_last_error(const smps_ctx *ctx);
 /* Bytes of device workspace the context currently holds (grow-only arena). */
 int smps_ctx_workspace_bytes(const smps_ctx *ctx, size_t *bytes);
+/* Exact split of a two-site tensor in the single-problem sweep (Sec. 2.3):
+ *   SMPS_SPLIT_AUTO (default): the method measured fastest for the size --
+ *     at present the one-sided Jacobi SVD for every size;
+ *   SMPS_SPLIT_JACOBI: the one-sided Jacobi SVD for every step;
+ *   SMPS_SPLIT_GRAM: vectors of at most 128 elements go through the Gram
+ *     matrix H = X^T X, its Householder tridiagonal form and a
+ *     divide-and-conquer eigensolver (the kept rows are eigenvectors of H,
+ *     the singular values the norms ||X v_i||); longer vectors use the
+ *     one-sided Jacobi SVD.
+ * Batched launches always use the one-sided Jacobi SVD.  Unknown method:
+ * SMPS_EINVAL. */
+enum { SMPS_SPLIT_AUTO = 0, SMPS_SPLIT_JACOBI = 1, SMPS_SPLIT_GRAM = 2 };
+int smps_ctx_set_split(smps_ctx *ctx, int method);
 /* Kernel timing with HIP events recorded on the context stream around every
-   launch of a category (0 = factorization, 1 = contractions).  on != 0 enables
+   launch of a category (0 = every factorization of the single-problem sweep,
+   1 = contractions, 2 = the factorizations of the largest square two-site
+   tensor of the run -- the bulk steps -- also counted in 0).  on != 0 enables
    it and clears the counters; smps_ctx_kernel_time returns the accumulated
    milliseconds and the number of timed launches of a category since then. */
 int smps_ctx_set_profiling(smps_ctx *ctx, int on);

@@ -26,7 +26,8 @@ MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
 
 # every symbol the header declares, in declaration order
 EXPORTS = [
-    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes", "smps_ctx_set_profiling",
+    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes", "smps_ctx_set_split",
+    "smps_ctx_set_profiling",
     "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
@@ -76,6 +77,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_ctx_destroy": (c_int, [vp]),
         "smps_last_error": (ctypes.c_char_p, [vp]),
         "smps_ctx_workspace_bytes": (c_int, [vp, POINTER(c_size_t)]),
+        "smps_ctx_set_split": (c_int, [vp, c_int]),
         "smps_ctx_set_profiling": (c_int, [vp, c_int]),
         "smps_ctx_kernel_time": (c_int, [vp, c_int, POINTER(c_double), POINTER(ctypes.c_longlong)]),
         "smps_mps_create": (c_int, [vp, c_int, ip, ip, c_int, POINTER(vp), POINTER(vp)]),
@@ -506,6 +508,10 @@ class Context:
         n = ctypes.c_longlong()
         self._check(self.lib.smps_ctx_kernel_time(self.h, int(category), byref(ms), byref(n)))
         return ms.value, n.value
+
+    def set_split(self, method: str) -> None:
+        """'auto' (the library's choice), 'jacobi' or 'gram' (Gram / tridiagonal split for short vectors)."""
+        self._check(self.lib.smps_ctx_set_split(self.h, {"auto": 0, "jacobi": 1, "gram": 2}[method]))
 
     def workspace_bytes(self) -> int:
         b = c_size_t()

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libseemps_hip.so")
 
-SOURCES = ["gemm.hip", "mpo_kernels.hip", "jacobi.hip", "util.hip", "sweep.hip", "abi.hip", "mlp.hip", "rsvd.hip", "autotune.hip", "dmrg.hip", "zapply.hip"]
+SOURCES = ["gemm.hip", "mpo_kernels.hip", "jacobi.hip", "util.hip", "sweep.hip", "abi.hip", "mlp.hip", "rsvd.hip", "autotune.hip", "dmrg.hip", "zapply.hip", "gtd.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC]

@@ -70,14 +70,15 @@ int prof_begin(smps_ctx* c, hipStream_t s) {
     return tok;
 }
 
-void prof_end(smps_ctx* c, hipStream_t s, int token, int category) {
+void prof_end(smps_ctx* c, hipStream_t s, int token, int category, int also) {
     if (token < 0) return;
     if (hipEventRecord(c->ev_pool[token + 1], s) != hipSuccess) return;
-    c->ev_pending[category & 1].emplace_back(token, token + 1);
+    if (category >= 0 && category < 3) c->ev_pending[category].emplace_back(token, token + 1);
+    if (also >= 0 && also < 3 && also != category) c->ev_pending[also].emplace_back(token, token + 1);
 }
 
 void prof_collect(smps_ctx* c) {
-    for (int cat = 0; cat < 2; ++cat) {
+    for (int cat = 0; cat < 3; ++cat) {
         for (auto& pr : c->ev_pending[cat]) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]) == hipSuccess) {
@@ -150,6 +151,7 @@ int smps_ctx_create(int device, void* hip_stream, smps_ctx** out) {
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SMPS_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return SMPS_EHIP;
     if (jacobi_init(device) != hipSuccess) return SMPS_EHIP;
+    if (gtd_init() != hipSuccess) return SMPS_EHIP;
     smps_ctx* c = new smps_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -179,7 +181,7 @@ int smps_ctx_set_profiling(smps_ctx* c, int on) {
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
     c->profiling = on != 0;
-    for (int cat = 0; cat < 2; ++cat) {
+    for (int cat = 0; cat < 3; ++cat) {
         c->prof_ms[cat] = 0.0;
         c->prof_n[cat] = 0;
     }
@@ -187,11 +189,19 @@ int smps_ctx_set_profiling(smps_ctx* c, int on) {
 }
 
 int smps_ctx_kernel_time(smps_ctx* c, int category, double* total_ms, long long* launches) {
-    if (!c || category < 0 || category > 1) return SMPS_EINVAL;
+    if (!c || category < 0 || category > 2) return SMPS_EINVAL;
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
     if (total_ms) *total_ms = c->prof_ms[category];
     if (launches) *launches = c->prof_n[category];
+    return SMPS_OK;
+}
+
+int smps_ctx_set_split(smps_ctx* c, int method) {
+    if (!c) return SMPS_EINVAL;
+    if (method != SMPS_SPLIT_AUTO && method != SMPS_SPLIT_JACOBI && method != SMPS_SPLIT_GRAM)
+        return fail(c, SMPS_EINVAL, "unknown split method");
+    c->split_method = method;
     return SMPS_OK;
 }
 
@@ -661,24 +671,44 @@ int smps_last_factor_log(const smps_ctx* c, int max_steps, int* kinds, int* step
 }
 
 // <a, b> by the transfer matrix E_{k+1} = a_k^T (E_k b_k)  (Sec. 2.4.4)
-int smps_scprod(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out) {
-    if (!c) return SMPS_EINVAL;
+}  // extern "C"
+
+namespace {
+
+int check_scprod_args(smps_ctx* c, const smps_mps* a, const smps_mps* b, const double* out) {
     if (!a || !b || !out) return fail(c, SMPS_EINVAL, "NULL argument");
     if (a->L != b->L) return fail(c, SMPS_EINVAL, "lengths differ");
     for (int k = 0; k < a->L; ++k)
         if (a->phys[k] != b->phys[k]) return fail(c, SMPS_EINVAL, "physical dimensions differ");
-    SMPS_HIP(c, hipSetDevice(c->device));
+    return SMPS_OK;
+}
+
+// Workspace of the transfer-matrix sweep: offsets of E0, E1 (largest
+// chi_a x chi_b) and F (largest chi_a d chi_b) and the total, in bytes.
+struct ScprodLayout {
+    size_t oE0, oE1, oF, total;
+};
+ScprodLayout scprod_layout(const smps_mps* a, const smps_mps* b) {
     size_t maxE = 1, maxF = 1;
     for (int k = 0; k < a->L; ++k) {
         maxE = std::max(maxE, (size_t)a->bonds[k + 1] * b->bonds[k + 1]);
         maxF = std::max(maxF, (size_t)a->bonds[k] * a->phys[k] * b->bonds[k + 1]);
     }
-    const size_t oE0 = 0, oE1 = (8 * maxE + 255) / 256 * 256, oF = 2 * oE1, tot = oF + 8 * maxF + 256;
-    int rc = ensure_arena(c, tot);
-    if (rc) return rc;
-    double* E0 = (double*)(c->arena + oE0);
-    double* E1 = (double*)(c->arena + oE1);
-    double* F = (double*)(c->arena + oF);
+    ScprodLayout l{};
+    l.oE0 = 0;
+    l.oE1 = (8 * maxE + 255) / 256 * 256;
+    l.oF = 2 * l.oE1;
+    l.total = l.oF + (8 * maxF + 255) / 256 * 256;
+    return l;
+}
+
+// <a|b> by the transfer-matrix sweep (Sec. 2.4.4) in the workspace `ws`;
+// the 1 x 1 result is left at *result_dev (a device address inside ws).
+int scprod_sweep(smps_ctx* c, const smps_mps* a, const smps_mps* b, char* ws, const ScprodLayout& lay,
+                 const double** result_dev) {
+    double* E0 = (double*)(ws + lay.oE0);
+    double* E1 = (double*)(ws + lay.oE1);
+    double* F = (double*)(ws + lay.oF);
     SMPS_HIP(c, launch_fill(E0, 1.0, 1, c->stream));
     for (int k = 0; k < a->L; ++k) {
         const int ca = a->bonds[k], cb = b->bonds[k], d = a->phys[k], ca2 = a->bonds[k + 1], cb2 = b->bonds[k + 1];
@@ -706,8 +736,27 @@ int smps_scprod(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out) 
         SMPS_HIP(c, launch_gemm(h, ca2, cb2, 1, c->stream, P_F64));
         std::swap(E0, E1);
     }
+    *result_dev = E0;
+    return SMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smps_scprod(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out) {
+    if (!c) return SMPS_EINVAL;
+    int rc = check_scprod_args(c, a, b, out);
+    if (rc) return rc;
+    SMPS_HIP(c, hipSetDevice(c->device));
+    const ScprodLayout lay = scprod_layout(a, b);
+    rc = ensure_arena(c, lay.total + 256);
+    if (rc) return rc;
+    const double* res = nullptr;
+    rc = scprod_sweep(c, a, b, c->arena, lay, &res);
+    if (rc) return rc;
     double r = 0.0;
-    SMPS_HIP(c, hipMemcpyAsync(&r, E0, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SMPS_HIP(c, hipMemcpyAsync(&r, res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     *out = r;
     return SMPS_OK;

@@ -135,6 +135,12 @@ hipError_t launch_right_mpo(const RightMpoDesc& d, int c_cap, hipStream_t s);
 hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags,
                          hipStream_t s);
 size_t jacobi_work_doubles(int nvec_cap, int len_cap);
+// Gram / tridiagonal / divide-and-conquer split (gtd.hip): rows of at most
+// 128 elements (and at most 1024 rows); `work` holds gtd_work_doubles doubles.
+bool gtd_supported(int nvec_cap, int len_cap);
+size_t gtd_work_doubles(int nvec_cap, int len_cap);
+hipError_t gtd_init();
+hipError_t launch_gtd(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, hipStream_t s);
 hipError_t jacobi_init(int device);
 int jacobi_lds_limit();
 int jacobi_lds_class(int len_cap);

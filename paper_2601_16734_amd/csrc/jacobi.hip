@@ -30,6 +30,7 @@
 #include <unordered_map>
 
 #include "common.h"
+#include "select.h"
 
 namespace smps {
 
@@ -50,33 +51,6 @@ __device__ __forceinline__ int tourney(int pos, int rd, int n2) {
     int x = pos - 1 + rd;  // < 2 (n2 - 1)
     if (x >= n2 - 1) x -= n2 - 1;
     return x + 1;
-}
-
-// Numerical rank floor: a vector whose norm is at most
-// u * max(nvec, len) * ||X||_F, with u the unit roundoff of the arithmetic that
-// produced X, is rounding noise of a rank-deficient matrix; it takes part in
-// no rotation and counts as a zero singular value.
-__device__ __forceinline__ double zero_floor2(double total2, int nv, int len, double u) {
-    const double f = u * (double)(nv > len ? nv : len);
-    return f * f * total2;
-}
-
-// Cross-lane move inside a row of 16 lanes (DPP), for a double.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the 16 lanes of a row; every lane ends with the identical value
-// (each step adds a disjoint partner, and addition is commutative).
-__device__ __forceinline__ double row_sum16(double x) {
-    x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]: partner lane ^ 1
-    x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]: partner lane ^ 2
-    x += dpp_mov<0x141>(x);  // row_half_mirror: quad 0 <-> quad 1, quad 2 <-> quad 3
-    x += dpp_mov<0x140>(x);  // row_mirror: lanes 0-7 <-> lanes 8-15
-    return x;
 }
 
 // Sum over the 8 lanes of a half row (quad pairs, then the half-row mirror).
@@ -383,106 +357,6 @@ static int elems_for(int len_cap) {
     if (len_cap <= 128) return 8;
     if (len_cap <= 256) return 16;
     return 0;
-}
-
-// Norms, order, rank rule and discarded weight for nv vectors; results in
-// LDS arrays sig (sorted order), perm, and the returned rank.  W may be in
-// LDS or global memory.  Must be called by all threads of the workgroup.
-__device__ int jacobi_select(const double* W, int nv, int len, int ld, double* sig_raw, double* sig_sorted,
-                             int* perm, const JacobiDesc& d, double* s_delta) {
-    const int tid = threadIdx.x;
-    // norms: a group of 16 lanes per vector
-    const int nt = blockDim.x;
-    const int g = 16, gl = tid & (g - 1), gi = tid / g, ngroups = nt / g;
-    for (int j = gi; j < nv; j += ngroups) {
-        const double* w = W + (size_t)j * ld;
-        double a = 0.0;
-        for (int i = gl; i < len; i += g) a = fma(w[i], w[i], a);
-        a = row_sum16(a);
-        if (gl == 0) sig_raw[j] = a;
-    }
-    __syncthreads();
-    // squared norms -> singular values, with the numerical rank floor
-    __shared__ double s_floor2;
-    if (tid == 0) {
-        double t2 = 0.0;
-        for (int j = 0; j < nv; ++j) t2 += sig_raw[j];
-        s_floor2 = zero_floor2(t2, nv, len, d.floor_eps);
-    }
-    __syncthreads();
-    for (int j = tid; j < nv; j += nt) {
-        const double a = sig_raw[j];
-        sig_raw[j] = a > s_floor2 ? (d.gram ? sqrt(sqrt(a)) : sqrt(a)) : 0.0;
-    }
-    __syncthreads();
-    // descending order with ties broken by index
-    for (int j = tid; j < nv; j += nt) {
-        const double sj = sig_raw[j];
-        int pos = 0;
-        for (int k = 0; k < nv; ++k) {
-            const double sk = sig_raw[k];
-            pos += (sk > sj) || (sk == sj && k < j);
-        }
-        perm[pos] = j;
-        sig_sorted[pos] = sj;
-    }
-    __syncthreads();
-    __shared__ int s_r;
-    if (tid == 0) {
-        // weight not represented by the computed values (zero unless an exact
-        // total is supplied), counted in every tail
-        double all = 0.0;
-        for (int j = nv - 1; j >= 0; --j) all += sig_sorted[j] * sig_sorted[j];
-        const double total = d.total_ext ? *d.total_ext : all;
-        const double missed = d.total_ext ? fmax(0.0, total - all) : 0.0;
-        int r;
-        if (d.mode == SMPS_TRUNC_REL_SV) {
-            r = 0;
-            const double thr = d.tol * sig_sorted[0];
-            for (int j = 0; j < nv; ++j) r += sig_sorted[j] > thr;
-        } else {
-            // smallest r >= 1 whose tail (summed from the smallest value up) fits
-            const double thr = d.tol * total;
-            double t = missed;
-            int cand = nv;
-            if (t <= thr) {
-                while (cand > 1) {
-                    const double tn = t + sig_sorted[cand - 1] * sig_sorted[cand - 1];
-                    if (tn <= thr) {
-                        t = tn;
-                        --cand;
-                    } else {
-                        break;
-                    }
-                }
-            }
-            r = cand;
-        }
-        if (r < 1) r = 1;
-        if (r > d.max_rank) r = d.max_rank;
-        if (r > nv) r = nv;
-        if (r > len) r = len;
-        double delta = 0.0;
-        for (int j = nv - 1; j >= r; --j) delta += sig_sorted[j] * sig_sorted[j];
-        delta += missed;
-        s_r = r;
-        *s_delta = delta;
-        if (d.log_delta) *d.log_delta = delta;
-        if (d.log_rank) *d.log_rank = r;
-        if (d.log_norm2) {
-            double kept = 0.0;
-            for (int j = r - 1; j >= 0; --j) kept += sig_sorted[j] * sig_sorted[j];
-            *d.log_norm2 = kept;
-        }
-        d.dims_out[d.rank_idx] = r;
-    }
-    __syncthreads();
-    if (d.log_spec)
-        for (int j = tid; j < 32; j += nt) d.log_spec[j] = j < nv ? sig_sorted[j] : 0.0;
-    for (int j = tid; j < nv; j += nt) d.sigma[j] = sig_sorted[j];
-    const int r = s_r;
-    __syncthreads();
-    return r;
 }
 
 // Kept rows: Q[i] = W[perm[i]] / s_i (a zero vector only occurs when the
@@ -1037,8 +911,11 @@ static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, di
 }
 
 hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
-    (void)work;
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
+    // exact splits of short rows: the Gram / tridiagonal / divide-and-conquer
+    // path when the caller provides its workspace
+    if (work && !d.gram && !d.accumulate && !d.total_ext && gtd_supported(nvec_cap, len_cap))
+        return launch_gtd(d, nvec_cap, len_cap, work, s);
     if (jacobi_fits_lds(nvec_cap, len_cap, d.accumulate != 0)) {
         launch_lds(d, nullptr, 1, elems_for(len_cap), lds_need(nvec_cap, len_cap, d.accumulate != 0), s,
                    d.accumulate != 0, nvec_cap);

@@ -14,6 +14,8 @@ struct smps_ctx {
     // grow-only workspace arena for apply/simplify/scprod
     char* arena = nullptr;
     size_t arena_bytes = 0;
+    // exact split of the single-problem sweep: SMPS_SPLIT_AUTO, _JACOBI or _GRAM
+    int split_method = 0;
     // exact-size cache of device blocks released by destroyed handles
     std::multimap<size_t, void*> pool;
     // pinned staging for small read-backs
@@ -37,10 +39,10 @@ struct smps_ctx {
     // optional per-category kernel timing (events recorded on the stream)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_pending[2];  // (start, stop) indices per category
+    std::vector<std::pair<int, int>> ev_pending[3];  // (start, stop) indices per category
     int ev_used = 0;
-    double prof_ms[2] = {0.0, 0.0};
-    long long prof_n[2] = {0, 0};
+    double prof_ms[3] = {0.0, 0.0, 0.0};
+    long long prof_n[3] = {0, 0, 0};
 };
 
 struct smps_mps {
@@ -74,7 +76,7 @@ int ensure_pinned(smps_ctx* c, size_t bytes);
 // off) that prof_end closes; prof_collect folds finished pairs into the totals
 // (call after the stream has been synchronised).
 int prof_begin(smps_ctx* c, hipStream_t s);
-void prof_end(smps_ctx* c, hipStream_t s, int token, int category);
+void prof_end(smps_ctx* c, hipStream_t s, int token, int category, int also = -1);
 void prof_collect(smps_ctx* c);
 smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds);
 

@@ -64,6 +64,7 @@ struct Plan {
     std::vector<size_t> o_accJ;  // per bond: J of the last accumulated factorization there
     size_t o_acctag = 0;         // per bond: validity tag of o_accJ (2 nvec + direction + 1)
     size_t o_tmp, o_theta, o_theta2, o_Q, o_carry, o_tmpB, o_sigma, o_perm;
+    size_t o_gtd = 0;  // workspace of the Gram / tridiagonal split (single path only)
     size_t o_ldelta, o_lrank, o_lspec, o_lnorm2, o_lsweeps;
     size_t o_R64a, o_R64b, o_XR64, o_Y64;
     // randomized factorization scratch (allocated only when it is requested)
@@ -349,8 +350,10 @@ struct Enq {
             case OP_RIGHT: return launch_right_mpo(op.r, op.cap0, s);
             case OP_JAC: {
                 const int tok = ctx ? prof_begin(ctx, s) : -1;
-                hipError_t e = launch_jacobi(op.jd, op.cap0, op.cap1, nullptr, at<int>(p.o_flag), s);
-                if (ctx) prof_end(ctx, s, tok, 0);
+                hipError_t e = launch_jacobi(op.jd, op.cap0, op.cap1, gtd_on(op.cap0, op.cap1) ? at<double>(p.o_gtd) : nullptr,
+                                             at<int>(p.o_flag), s);
+                // category 2 also counts the splits of the largest (bulk) two-site tensor
+                if (ctx) prof_end(ctx, s, tok, 0, op.cap0 == p.max_nvec && op.cap1 == p.max_nvec ? 2 : -1);
                 return e;
             }
             case OP_COPY: return launch_copy(op.cp.src, op.cp.dst, op.cp.dims, op.cp.a, op.cp.b, op.cap0, s);
@@ -666,6 +669,7 @@ struct Enq {
         // direction left (the kernel falls back to theta when that J's tag does
         // not match); any other step by the bond's basis
         const bool acc_warm = acc && p.o_accJ[k] != 0;
+        if (rotate && gtd_on(nvec_cap, len_cap)) rotate = false;  // H = X^T X does not depend on it
         if (rotate) {
             X = at<double>(p.o_theta2);
             hipError_t e = gemm(at(acc_warm ? p.o_accJ[k] : p.o_basis[k]), T_F64, theta, T_F64, X, T_F64, nvec, len,
@@ -694,10 +698,17 @@ struct Enq {
     // matrix); exact factorizations in the LDS kernel only.
     bool use_acc(int need_side, int other_side) const {
         return st.factorization == SMPS_FACT_SVD && need_side < other_side &&
-               jacobi_fits_lds(need_side, other_side, true);
+               jacobi_fits_lds(need_side, other_side, true) && !gtd_on(other_side, need_side);
     }
 
     int eval_host(DimExpr x) const { return x.idx < 0 ? x.mul : x.mul * hdims[x.idx]; }
+
+    // The exact split of nvec_cap vectors of len_cap elements goes through the
+    // Gram matrix and a tridiagonal eigensolver (single path, short vectors);
+    // it needs neither a warm start nor the accumulated orientation.
+    bool gtd_on(int nvec_cap, int len_cap) const {
+        return !rec && ctx && ctx->split_method == SMPS_SPLIT_GRAM && p.o_gtd && gtd_supported(nvec_cap, len_cap);
+    }
 
     hipError_t run() const {
         const int L = p.L;
@@ -1001,6 +1012,10 @@ static int run_terms(smps_ctx* c, int n, const double* w, const smps_mpo* const*
     if (n > 1 || w[0] != 1.0)
         plan_terms(p, std::vector<const smps_mpo*>(U, U + n), std::vector<const smps_mps*>(v, v + n),
                    std::vector<double>(w, w + n), lay);
+    if (c->split_method == SMPS_SPLIT_GRAM) {
+        const int nc = std::min(p.max_nvec, 1024), lc = std::min(p.max_nvec, 128);
+        if (gtd_supported(nc, lc)) p.o_gtd = lay.add(8 * gtd_work_doubles(nc, lc));
+    }
     int rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     if (st.factorization == SMPS_FACT_RSVD_MLP && !mlp_ready(c))

@@ -373,6 +373,27 @@ def workload_decaying(rep: int = 0, L: int = 64, chi: int = 512, D: int = 8) -> 
     return Workload(f"decaying_L{L}_chi{chi}_D{D}", mps, mpo, chi, 1e-10, meta={"taus": taus})
 
 
+def product_mpo(rng: np.random.Generator, L: int, d: int, spread: float = 0.3) -> list[np.ndarray]:
+    """Bond-1 MPO of independent local operators I + spread * N(0,1) (a product
+    operator: it rescales the bond spectra of a state but does not flatten them)."""
+    out = []
+    for _ in range(L):
+        m = np.eye(d) + spread * rng.standard_normal((d, d))
+        out.append(np.ascontiguousarray(m.reshape(1, d, d, 1)))
+    return out
+
+
+def workload_decaying_tol(rep: int = 0, L: int = 32, chi: int = 512, tau_range=(20.0, 40.0)) -> Workload:
+    """Tolerance-bound variant of the decaying-spectrum workload: L=32, d=2,
+    chi=512 MPS with spectra ~ exp(-j/tau), tau ~ U[20,40] per bond, under a
+    product operator; at tol 1e-10 the kept ranks (about 11.5 tau) fall below
+    the cap of 512, so the tolerance, not the cap, decides them."""
+    rng = rng_for(6, rep)
+    mps, taus = decaying_spectrum_mps(rng, L, 2, chi, tau_range=tau_range)
+    mpo = product_mpo(rng, L, 2)
+    return Workload(f"decaying_tol_L{L}_chi{chi}", mps, mpo, chi, 1e-10, sweeps=2, meta={"taus": taus})
+
+
 # ---- rank-predictor inputs -------------------------------------------------------
 def mlp_params(rng: np.random.Generator, n: int = 6337, scale: float = 0.2) -> np.ndarray:
     """Random FP32 parameter vector for the 32-64-64-1 rank predictor."""

@@ -58,17 +58,22 @@ def test_batched_equals_single_and_oracle(ctx):
 
 
 def test_batched_matches_single_bitwise_on_lds_path(ctx):
+    # batched launches use the one-sided Jacobi split; so does the single path here
     ws = small_batch()
     vs, Us = upload(ctx, ws)
     st = B.strategy(16, 1e-10, sweeps=2)
     outs, errs = ctx.mpo_apply_batched(Us, vs, st)
-    for i in range(len(ws)):
-        one, err1 = ctx.mpo_apply(Us[i], vs[i], st)
-        a, b = outs[i].read(), one.read()
-        assert [t.shape for t in a] == [t.shape for t in b]
-        for x, y in zip(a, b):
-            np.testing.assert_array_equal(x, y)
-        assert errs[i] == err1
+    ctx.set_split("jacobi")
+    try:
+        for i in range(len(ws)):
+            one, err1 = ctx.mpo_apply(Us[i], vs[i], st)
+            a, b = outs[i].read(), one.read()
+            assert [t.shape for t in a] == [t.shape for t in b]
+            for x, y in zip(a, b):
+                np.testing.assert_array_equal(x, y)
+            assert errs[i] == err1
+    finally:
+        ctx.set_split("auto")
 
 
 def test_batched_graph_replay_is_deterministic(ctx):

@@ -1,0 +1,120 @@
+"""The exact split through the Gram matrix (tridiagonal divide and conquer)
+against the one-sided Jacobi SVD and the oracle, whole runs of apply +
+compression (Sec. 2.3 split, Sec. 2.5 sweep): per-step ranks and discarded
+weights, the final state's norm and its fidelity with the oracle's state."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mps as om
+from paper_2601_16734_amd import binding as B
+from tests.gpu_helpers import error_bound_slack
+
+pytestmark = pytest.mark.gpu
+
+
+def _norms_match(a, b, tol):
+    return abs(a - b) <= tol * abs(b)
+
+
+def _run(ctx, w, sweeps, split, precision="fp64"):
+    ctx.set_split(split)
+    try:
+        U, v = ctx.mpo_create(w.mpo), ctx.mps_create(w.mps)
+        out, err = ctx.mpo_apply(U, v, B.strategy(w.max_bond, w.tol, sweeps=sweeps, precision=precision))
+        deltas, ranks, spec = ctx.last_log()
+        info = ctx.last_info()
+        got = out.read()
+        out.destroy()
+        U.destroy()
+        v.destroy()
+        return got, info, deltas, ranks, spec, err
+    finally:
+        ctx.set_split("auto")
+
+
+def _fidelity_loss(a, b):
+    return 1.0 - abs(om.scprod(a, b)) / math.sqrt(om.scprod(a, a) * om.scprod(b, b))
+
+
+CASES = {
+    "laplacian_n10_chi8": (lambda: synth.workload_laplacian_small(0), 4),
+    "random_mpo_n20_chi64": (lambda: synth.workload_random_mpo(0), 4),
+    "random_mpo_n12_chi32_D4": (lambda: synth.workload_random_mpo(1, L=12, chi=32, D=4), 3),
+    "decaying_L14_chi64": (lambda: synth.Workload(
+        "decaying", synth.decaying_spectrum_mps(synth.rng_for(7, 0), 14, 2, 64, tau_range=(3.0, 8.0))[0],
+        synth.product_mpo(synth.rng_for(7, 1), 14, 2), 64, 1e-10), 2),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_gram_split_whole_run_matches_oracle_and_jacobi(ctx, name):
+    make, sweeps = CASES[name]
+    w = make()
+    ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=sweeps)
+    got, info, deltas, ranks, spec, err = _run(ctx, w, sweeps, "gram")
+    jg, jinfo, jdeltas, jranks, _, _ = _run(ctx, w, sweeps, "jacobi")
+    assert list(ranks) == ref.step_ranks
+    assert list(jranks) == ref.step_ranks
+    for k in range(len(ref.deltas)):
+        scale = ref.norms2[k] + ref.deltas[k]
+        assert abs(deltas[k] - ref.deltas[k]) <= 1e-10 * scale + 1e-8 * ref.deltas[k], k
+        assert abs(spec[k][0] - ref.spectra[k][3][0]) <= 1e-8 * ref.spectra[k][3][0], k
+    assert _norms_match(info["norm"], ref.norm, 1e-10)
+    assert _norms_match(info["norm"], jinfo["norm"], 1e-10)
+    assert _fidelity_loss(got, ref.mps) <= 1e-10
+    assert _fidelity_loss(got, jg) <= 1e-10
+    assert abs(err - ref.error_bound) <= 1e-6 * ref.error_bound + 1e-12 + error_bound_slack(ref)
+    assert abs(err - float(np.sum(np.sqrt(np.maximum(deltas, 0.0))))) <= 1e-12 * max(err, 1e-300)
+    # every site but the centre is a right isometry, exactly orthonormal rows
+    for t in got[1:]:
+        M = t.reshape(t.shape[0], -1)
+        assert np.abs(M @ M.T - np.eye(M.shape[0])).max() <= 1e-12
+
+
+def test_gram_split_exact_apply_is_the_dense_product(ctx):
+    # bonds large enough for the exact product and tol 0: psi = U v (Sec. 2.4.2)
+    from oracle import dense
+    rng = np.random.default_rng(23)
+    mps = synth.random_mps(rng, 8, 2, 4)
+    mpo = synth.random_mpo(rng, 8, 2, 3)
+    w = synth.Workload("exact", mps, mpo, 16, 0.0)
+    got, info, *_ = _run(ctx, w, 2, "gram")
+    uv = dense.mpo_to_dense(mpo) @ dense.mps_to_dense(mps)
+    np.testing.assert_allclose(dense.mps_to_dense(got), uv, rtol=0, atol=1e-12 * np.abs(uv).max())
+
+
+def test_gram_split_rank_deficient_and_zero_states(ctx):
+    # a product state under a product operator: every two-site tensor has rank 1
+    rng = np.random.default_rng(5)
+    mps = [rng.standard_normal((1, 2, 1)) for _ in range(10)]
+    mpo = synth.product_mpo(rng, 10, 2)
+    w = synth.Workload("product", mps, mpo, 8, 1e-12)
+    ref = om.apply_simplify(w.mpo, w.mps, w.max_bond, w.tol, sweeps=2)
+    got, info, deltas, ranks, *_ = _run(ctx, w, 2, "gram")
+    assert set(ranks) == {1} and ref.step_ranks == list(ranks)
+    assert _norms_match(info["norm"], ref.norm, 1e-12)
+    # the zero state: norm 0, rank 1 everywhere, no error
+    zero = [np.zeros_like(t) for t in synth.random_mps(rng, 8, 2, 4)]
+    wz = synth.Workload("zero", zero, synth.random_mpo(rng, 8, 2, 2), 8, 1e-10)
+    gz, iz, dz, rz, *_ = _run(ctx, wz, 1, "gram")
+    assert iz["norm"] == 0.0 and set(rz) == {1} and not np.any(dz)
+
+
+def test_gram_split_rejects_non_finite_input(ctx):
+    w = synth.workload_random_mpo(0, L=8, chi=16, D=2)
+    w.mps[3] = w.mps[3].copy()
+    w.mps[3][0, 0, 0] = np.nan
+    U, v = ctx.mpo_create(w.mpo), ctx.mps_create(w.mps)
+    ctx.set_split("gram")
+    try:
+        with pytest.raises(B.SmpsError) as e:
+            ctx.mpo_apply(U, v, B.strategy(16, 1e-10, sweeps=1))
+        assert e.value.code == B.ENUMERIC
+    finally:
+        ctx.set_split("auto")
+    U.destroy()
+    v.destroy()

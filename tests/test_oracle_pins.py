@@ -290,6 +290,69 @@ def test_tt_svd_reference_quality():
     assert var_err <= 2 * tt_err
 
 
+def test_tt_svd_full_rank_reconstructs_a_random_vector():
+    # bonds up to 2^5 = 32 cover every unfolding of a 10-qubit vector exactly
+    rng = np.random.default_rng(41)
+    v = rng.standard_normal(2 ** 10)
+    tt = om.tt_svd(v, [2] * 10, 32)
+    assert [t.shape[2] for t in tt[:-1]] == [2, 4, 8, 16, 32, 16, 8, 4, 2]
+    np.testing.assert_allclose(dense.mps_to_dense(tt), v, rtol=0, atol=1e-14 * np.abs(v).max())
+    # every site but the last is a left isometry (Sec. 2.3 canonical form)
+    for t in tt[:-1]:
+        M = t.reshape(-1, t.shape[2])
+        assert np.abs(M.T @ M - np.eye(M.shape[1])).max() <= 1e-13
+
+
+def _basis_superposition(coeffs, patterns):
+    v = np.zeros(2 ** len(patterns[0]))
+    for c, p in zip(coeffs, patterns):
+        v[int(p, 2)] += c  # MSB first (Eq. binary)
+    return v
+
+
+def test_tt_svd_and_unfolding_bound_on_hand_built_spectra():
+    # v = sum_j c_j |b_j> over four orthogonal product states.  For cuts 2..8
+    # the prefixes and suffixes of the four patterns are all distinct, so the
+    # Schmidt values there are exactly |c_j|; at cuts 1 and 9 two patterns
+    # share each prefix (suffix) and the rank is 2.  Keeping 2 (3) states the
+    # smallest weight beyond the cap is c_2^2 + c_3^2 (c_3^2) -- by hand.
+    c = np.array([0.8, 0.5, 0.3, 0.1])
+    pats = ["0000000000", "1111111111", "0101010101", "1010101010"]
+    v = _basis_superposition(c, pats)
+    assert om.unfolding_tail_bound(v, [2] * 10, 2) == pytest.approx(0.3 ** 2 + 0.1 ** 2, rel=1e-14)
+    assert om.unfolding_tail_bound(v, [2] * 10, 3) == pytest.approx(0.1 ** 2, rel=1e-12)
+    assert om.unfolding_tail_bound(v, [2] * 10, 4) <= 1e-28
+    # TT-SVD truncates only at cut 2, where the kept singular vectors are the
+    # basis states of the two largest terms: the approximation is exactly
+    # c_0 |b_0> + c_1 |b_1> and the error meets the bound (Eckart-Young)
+    tt2 = om.tt_svd(v, [2] * 10, 2)
+    np.testing.assert_allclose(dense.mps_to_dense(tt2), _basis_superposition(c[:2], pats[:2]), atol=1e-15)
+    err2 = float(np.sum((dense.mps_to_dense(tt2) - v) ** 2))
+    assert err2 == pytest.approx(0.3 ** 2 + 0.1 ** 2, rel=1e-13)
+    err3 = float(np.sum((dense.mps_to_dense(om.tt_svd(v, [2] * 10, 3)) - v) ** 2))
+    assert err3 == pytest.approx(0.1 ** 2, rel=1e-12)
+
+
+def test_tt_svd_error_is_the_tail_at_the_only_truncated_cut():
+    # a 10-qubit vector with prescribed Schmidt values s_j = 2^-j/2 at the
+    # middle cut (random orthonormal factors on both halves): caps of 16 < 20
+    # < 32 truncate that cut only, so TT-SVD's error and the unfolding bound
+    # both equal sum_{j >= 20} s_j^2 exactly
+    rng = np.random.default_rng(7)
+    s = 2.0 ** (-np.arange(32) / 2.0)
+    U, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    W, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    v = (U * s[None, :]) @ W.T
+    v = v.reshape(-1)
+    tail = float(np.sum(s[20:] ** 2))
+    tt = om.tt_svd(v, [2] * 10, 20)
+    err = float(np.sum((dense.mps_to_dense(tt) - v) ** 2))
+    assert err == pytest.approx(tail, rel=1e-9)
+    assert om.unfolding_tail_bound(v, [2] * 10, 20) == pytest.approx(tail, rel=1e-9)
+    # a dropped tail term or a shifted cut would miss by s_19^2 or s_20^2
+    assert abs(err - tail) < 1e-3 * s[20] ** 2
+
+
 # ---------------------------------------------------------------- rank-predictor network (oracle side)
 
 def test_bf16_rounding_hand_values():
