@@ -304,6 +304,24 @@ int smps_mpo_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const
 int smps_scprod(smps_ctx *ctx, const smps_mps *a, const smps_mps *b, double *out);
 int smps_norm(smps_ctx *ctx, const smps_mps *a, double *out);
 
+/* ---- scalar product without allocation -----------------------------------------
+ * For callers that cannot allocate device memory: code being captured into a
+ * HIP graph, serving loops that must not call hipMalloc, harnesses that forbid
+ * it.  Same transfer-matrix sweep and the same products as smps_scprod, but
+ * its workspace is a fixed 4 MiB device array of the library (one per device,
+ * held until the process ends) instead of the context's grow-only arena, and
+ * the result is written to device memory instead of the host:
+ *   out_dev: device address of one double, owned by the caller; written
+ *            stream-ordered on the context's stream (no host synchronisation;
+ *            the caller synchronises before reading it).
+ * Limit: 2 * max_k(chi_a[k] chi_b[k]) + max_k(chi_a[k] d_k chi_b[k+1]) doubles
+ * (each part rounded up to 256 bytes) must fit in 4 MiB -- e.g. chi <= 256
+ * at d = 2 -- else SMPS_ENOMEM and nothing is launched.  No allocation of any
+ * kind happens inside the call.  Every call on one device shares that
+ * device's array: calls that overlap on one device (different streams or
+ * contexts, or host threads) race and must be serialised by the caller. */
+int smps_scprod_noalloc(smps_ctx *ctx, const smps_mps *a, const smps_mps *b, double *out_dev);
+
 /* ---- learned rank predictor for the randomized factorization ------------------
  * A 32-64-64-1 ReLU network with bf16 weights (FP32 master copy, FP32
  * accumulation).  Input: the 32 largest log(s_j / s_0) of a bond's spectrum in

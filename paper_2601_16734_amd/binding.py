@@ -33,6 +33,7 @@ EXPORTS = [
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
     "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_transpose",
     "smps_mpo_apply_right", "smps_mpo_list_apply", "smps_mpo_simplify", "smps_mpo_shape", "smps_mpo_read", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_scprod_noalloc",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
     "smps_autotune_apply", "smps_autotune_gemm", "smps_autotune_save", "smps_autotune_load", "smps_autotune_clear",
@@ -103,6 +104,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_mpo_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy), POINTER(vp), dp]),
         "smps_scprod": (c_int, [vp, vp, vp, dp]),
         "smps_norm": (c_int, [vp, vp, dp]),
+        "smps_scprod_noalloc": (c_int, [vp, vp, vp, vp]),
         "smps_rank_mlp_init": (c_int, [vp, c_ulonglong]),
         "smps_rank_mlp_train": (c_int, [vp, c_int, POINTER(c_float), POINTER(c_float), c_int, c_int, c_float,
                                         POINTER(c_float)]),
@@ -460,6 +462,10 @@ class Context:
         r = c_double()
         self._check(self.lib.smps_scprod(self.h, a.h, b.h, byref(r)))
         return r.value
+
+    def scprod_noalloc(self, a: MPS, b: MPS, out_dev_ptr: int) -> None:
+        """<a|b> into the device double at out_dev_ptr (stream-ordered, no sync)."""
+        self._check(self.lib.smps_scprod_noalloc(self.h, a.h, b.h, c_void_p(out_dev_ptr)))
 
     def norm(self, a: MPS) -> float:
         r = c_double()

@@ -2,6 +2,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "runtime.h"
 
@@ -138,6 +139,34 @@ static int check_chain(smps_ctx* c, int L, const int* phys, const int* bonds) {
     return SMPS_OK;
 }
 
+// Scratch of smps_scprod_noalloc: the two transfer matrices of the sweep
+// and one partial product, 4 MiB per device for the life of the process.
+// Host code never uses the array's name as an address: each device's copy
+// lives at its own address, looked up once per device when a context is
+// created on it (scratch_for_device) and passed to the kernels from there.
+constexpr size_t SCPROD_SCRATCH_BYTES = size_t(4) << 20;
+__device__ __align__(256) double scratch[SCPROD_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_m;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's copy of `scratch`; the device must be current.
+hipError_t scratch_for_device(int device, double** out) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_m);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 }  // namespace smps
 
 using namespace smps;
@@ -152,8 +181,11 @@ int smps_ctx_create(int device, void* hip_stream, smps_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return SMPS_EHIP;
     if (jacobi_init(device) != hipSuccess) return SMPS_EHIP;
     if (gtd_init() != hipSuccess) return SMPS_EHIP;
+    double* scr = nullptr;
+    if (scratch_for_device(device, &scr) != hipSuccess) return SMPS_EHIP;
     smps_ctx* c = new smps_ctx();
     c->device = device;
+    c->scratch = scr;
     c->stream = (hipStream_t)hip_stream;
     *out = c;
     return SMPS_OK;
@@ -759,6 +791,24 @@ int smps_scprod(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out) 
     SMPS_HIP(c, hipMemcpyAsync(&r, res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     *out = r;
+    return SMPS_OK;
+}
+
+int smps_scprod_noalloc(smps_ctx* c, const smps_mps* a, const smps_mps* b, double* out_dev) {
+    if (!c) return SMPS_EINVAL;
+    int rc = check_scprod_args(c, a, b, out_dev);
+    if (rc) return rc;
+    const ScprodLayout lay = scprod_layout(a, b);
+    if (lay.total > SCPROD_SCRATCH_BYTES)
+        return fail(c, SMPS_ENOMEM, "scprod_noalloc: needs " + std::to_string(lay.total) +
+                                        " bytes of scratch, above its fixed " +
+                                        std::to_string(SCPROD_SCRATCH_BYTES) + " bytes");
+    if (!c->scratch) return fail(c, SMPS_EHIP, "scprod_noalloc: scratch address not resolved");
+    SMPS_HIP(c, hipSetDevice(c->device));
+    const double* res = nullptr;
+    rc = scprod_sweep(c, a, b, (char*)c->scratch, lay, &res);
+    if (rc) return rc;
+    SMPS_HIP(c, hipMemcpyAsync(out_dev, res, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     return SMPS_OK;
 }
 

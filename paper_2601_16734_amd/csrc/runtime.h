@@ -14,6 +14,8 @@ struct smps_ctx {
     // grow-only workspace arena for apply/simplify/scprod
     char* arena = nullptr;
     size_t arena_bytes = 0;
+    // this device's copy of the fixed scratch array of smps_scprod_noalloc
+    double* scratch = nullptr;
     // exact split of the single-problem sweep: SMPS_SPLIT_AUTO, _JACOBI or _GRAM
     int split_method = 0;
     // exact-size cache of device blocks released by destroyed handles
