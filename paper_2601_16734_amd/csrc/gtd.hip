@@ -30,6 +30,7 @@
 namespace smps {
 
 constexpr int GTD_NT = 1024;  // threads of the eigensolver workgroup
+typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int GTD_MAX_N = 128;
 
 // rows of the 16-lane DPP groups
@@ -363,11 +364,12 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
     GtdLds s = gtd_carve(sm, n);
     double* A = s.A;
     __shared__ int s_bad;
+    __shared__ double s_tau[2], s_kc;
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int i = grp; i < n; i += GTD_NT / 16)
         for (int j = gl; j < n; j += 16) {
-            const double v = g.H[i * n + j];
+            const double v = g.H[(size_t)i * n + j];
             if (!isfinite(v)) s_bad = 1;
             A[i * ld + j] = v;
         }
@@ -378,18 +380,25 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
         if (tid == 0 && g.status) atomicOr(g.status, 1);
         return;
     }
-    // ---- 1. Householder reduction to tridiagonal form (lower, column k)
-    for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        // x = A[k+1.., k]; every wave forms the reflector redundantly (same order)
-        // (column k below the diagonal = row k right of it: the block stays symmetric)
-        const double* xk = A + k * ld + (k + 1);
+    // ---- 1. Householder reduction to tridiagonal form, H in LDS (row stride
+    // n + 1).  The update keeps H exactly symmetric, so column r below the
+    // diagonal is read as row r right of it.  The 16-lane group that owns row
+    // r once it is final forms its reflector (beta, tau and v, the last stored
+    // over row r right of the diagonal for the back-transformation) and hands
+    // v to the next step through vbuf[r & 1]; K = tau/2 p^T v and w = p - K v
+    // are formed by wave 0.
+    double* vbuf[2] = {s.vv, s.zl};
+    double* wv = s.dl;
+    // reflector of row r (called by one whole 16-lane group)
+    auto reflector = [&](int r) {
+        double* row = A + r * ld;
+        if (gl == 0) s.d[r] = row[r];
+        if (r + 1 >= n) return;
         double part = 0.0;
-        for (int i = 1 + lane; i < m; i += 64) part = fma(xk[i], xk[i], part);
-        const double xn2 = sum64(part);
-        const double x0 = xk[0];
+        for (int j = r + 2 + gl; j < n; j += 16) part = fma(row[j], row[j], part);
+        const double xn2 = sum16(part), x0 = row[r + 1];
         double beta, tau, scale;
-        if (xn2 == 0.0) {
+        if (xn2 == 0.0 || r + 2 >= n) {
             beta = x0;
             tau = 0.0;
             scale = 0.0;
@@ -398,43 +407,51 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
             tau = (beta - x0) / beta;
             scale = 1.0 / (x0 - beta);
         }
-        if (tid == 0) {
-            s.d[k] = A[k * ld + k];
-            s.e[k] = beta;
-            s.tau[k] = tau;
+        double* vout = vbuf[r & 1];
+        for (int j = r + 1 + gl; j < n; j += 16) {
+            const double v = j == r + 1 ? 1.0 : (tau != 0.0 ? row[j] * scale : 0.0);
+            vout[j - r - 1] = v;
+            row[j] = v;
         }
+        if (gl == 0) {
+            s.e[r] = beta;
+            s.tau[r] = tau;
+            s_tau[r & 1] = tau;
+        }
+    };
+    if (grp == 0) reflector(0);
+    __syncthreads();
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        const double tau = s_tau[k & 1];
+        const double* vv = vbuf[k & 1];
         if (tau != 0.0) {
-            // p = tau S v (S = trailing block), one 16-lane group per row
+            // p = tau S v, S the trailing block; one 16-lane group per row
             for (int i = grp; i < m; i += GTD_NT / 16) {
                 const double* row = A + (k + 1 + i) * ld + (k + 1);
                 double acc = 0.0;
-                for (int j = gl; j < m; j += 16) {
-                    const double vj = j == 0 ? 1.0 : xk[j] * scale;
-                    acc = fma(row[j], vj, acc);
-                }
+                for (int j = gl; j < m; j += 16) acc = fma(row[j], vv[j], acc);
                 acc = sum16(acc);
-                if (gl == 0) {
-                    const double vi = i == 0 ? 1.0 : xk[i] * scale;
-                    s.pp[i] = tau * acc;
-                    s.vv[i] = vi;
-                }
+                if (gl == 0) s.pp[i] = tau * acc;
             }
             __syncthreads();
-            // K = tau/2 p^T v (every wave, same order), w = p - K v
-            double pk = 0.0;
-            for (int i = lane; i < m; i += 64) pk = fma(s.pp[i], s.vv[i], pk);
-            const double Kc = 0.5 * tau * sum64(pk);
-            for (int i = grp; i < m; i += GTD_NT / 16) {
-                const double vi = s.vv[i], wi = s.pp[i] - Kc * vi;
-                double* row = A + (k + 1 + i) * ld + (k + 1);
-                for (int j = gl; j < m; j += 16) {
-                    const double vj = s.vv[j], wj = s.pp[j] - Kc * vj;
-                    // (v_i w_j) + (w_i v_j): the same two products in either order,
-                    // so the block stays exactly symmetric
-                    row[j] -= (vi * wj) + (wi * vj);
-                }
+            if (tid < 64) {
+                double pk = 0.0;
+                for (int i = lane; i < m; i += 64) pk = fma(s.pp[i], vv[i], pk);
+                const double Kc = 0.5 * tau * sum64(pk);
+                for (int i = lane; i < m; i += 64) wv[i] = s.pp[i] - Kc * vv[i];
             }
-            for (int i = tid; i < m; i += GTD_NT) g.refl[(size_t)k * n + k + 1 + i] = s.vv[i];
+            __syncthreads();
+            // S -= (v_i w_j) + (w_i v_j): the same two products in either order,
+            // so the block stays exactly symmetric
+            for (int i = grp; i < m; i += GTD_NT / 16) {
+                const double vi = vv[i], wi = wv[i];
+                double* row = A + (k + 1 + i) * ld + (k + 1);
+                for (int j = gl; j < m; j += 16) row[j] -= (vi * wv[j]) + (wi * vv[j]);
+                if (i == 0) reflector(k + 1);  // row k + 1 is final: the next step's reflector
+            }
+        } else if (grp == 0) {
+            reflector(k + 1);
         }
         __syncthreads();
     }
@@ -448,6 +465,10 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
         s.tau[n - 1] = 0.0;
     }
     __syncthreads();
+    // reflector k sits in row k right of the diagonal; zero elsewhere
+    for (int k = grp; k + 2 < n; k += GTD_NT / 16)
+        if (s.tau[k] != 0.0)
+            for (int j = gl; j < n; j += 16) g.refl[(size_t)k * n + j] = j > k ? A[k * ld + j] : 0.0;
     // ---- 2. divide and conquer on (d, e), leaves of one row.  Every e_i
     // couples one split, so a leaf carries d_i - |e_{i-1}| - |e_i|.  Qc row c
     // is eigenvector c of its node (entries at the node's rows).
@@ -578,15 +599,20 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
                 }
             }
             if (pj >= 0) s.ndf[a + K++] = pj;
-            for (int i = 0; i < K; ++i) {
-                const int x = s.ndf[a + i];
-                s.dl[a + i] = s.ds[a + x];
-                s.zl[a + i] = s.zs[a + x];
-                s.zh[a + i] = s.zs[a + x] * s.zs[a + x];
-            }
             s.nk[q] = K;
             s.nr[q] = nr;
             s.nd[q] = nd;
+        }
+        __syncthreads();
+        // the non-deflated values and weights in ascending order
+        for (int x = tid; x < n; x += GTD_NT) {
+            int a, b, q;
+            gtd_locate(n, t, x, &a, &b, &q);
+            if (b - a < 2 || x - a >= s.nk[q]) continue;
+            const int p = s.ndf[x];
+            s.dl[x] = s.ds[a + p];
+            s.zl[x] = s.zs[a + p];
+            s.zh[x] = s.zs[a + p] * s.zs[a + p];
         }
         __syncthreads();
         if (S > 32)
@@ -614,38 +640,65 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
         __syncthreads();
         // new vectors: eigenvector c of the node (row a + fp(c) of Qn) at node
         // row r is sum over the block's columns col of Qc[a + col][a + r] Y[ip(col)][c],
-        // where only columns of the child that owns row r contribute; four rows
-        // per work item
-        for (int x = tid; x < n * ((S + 3) / 4); x += GTD_NT) {
-            const int xr = x / ((S + 3) / 4), tile = x - xr * ((S + 3) / 4);
-            int a, b, q;
-            gtd_locate(n, t, xr, &a, &b, &q);
-            const int sz = b - a;
-            const int r0 = 4 * tile;
-            if (sz < 2 || r0 >= sz) continue;
-            const int m = sz / 2, c = xr - a;
-            const double* Y = s.A + (size_t)a * S;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            const int r1 = min(r0 + 4, sz);
-            if (r1 <= m || r0 >= m) {
-                const int c0 = r0 >= m ? m : 0, c1 = r0 >= m ? sz : m;
-                for (int col = c0; col < c1; ++col) {
-                    const double y = Y[(size_t)s.ip[a + col] * sz + c];
-                    const double* qr = Qc + (size_t)(a + col) * n + a;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (r0 + u < r1) acc[u] = fma(qr[r0 + u], y, acc[u]);
+        // where only columns of the child that owns row r contribute
+        if (S >= 32) {
+            // FP64 MFMA 16 x 16 x 4 tiles (c, r) over the owning child's columns;
+            // each wave takes whole tiles
+            const int wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+            for (int q = 0; q < (1 << t); ++q) {
+                int a = 0, b = n;
+                for (int l = t - 1; l >= 0; --l) {
+                    const int mid = a + (b - a) / 2;
+                    if ((q >> l) & 1)
+                        a = mid;
+                    else
+                        b = mid;
                 }
-            } else {
+                const int sz = b - a;
+                if (sz < 2) continue;
+                const int m = sz / 2, ct = (sz + 15) / 16, rt0 = (m + 15) / 16, rt1 = (sz - m + 15) / 16;
+                const double* Y = s.A + (size_t)a * S;
+                for (int tl = wave; tl < ct * (rt0 + rt1); tl += GTD_NT / 64) {
+                    const int ci = tl / (rt0 + rt1), ri = tl - ci * (rt0 + rt1);
+                    const bool top = ri < rt0;
+                    const int r0 = top ? 16 * ri : m + 16 * (ri - rt0), rend = top ? m : sz;
+                    const int k0 = top ? 0 : m, k1 = top ? m : sz, c0 = 16 * ci;
+                    v4d acc = {0.0, 0.0, 0.0, 0.0};
+                    for (int kk = k0; kk < k1; kk += 4) {
+                        const int col = kk + lk, c = c0 + li, r = r0 + li;
+                        const double av = (col < k1 && c < sz) ? Y[(size_t)s.ip[a + col] * sz + c] : 0.0;
+                        const double bv = (col < k1 && r < rend) ? Qc[(size_t)(a + col) * n + a + r] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                    }
+                    // v_mfma_f64_16x16x4 returns rows lk + 4 v, column li
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = c0 + lk + 4 * v, r = r0 + li;
+                        if (c < sz && r < rend) Qn[(size_t)(a + s.fp[a + c]) * n + a + r] = acc[v];
+                    }
+                }
+            }
+        } else {
+            for (int x = tid; x < n * ((S + 3) / 4); x += GTD_NT) {
+                const int xr = x / ((S + 3) / 4), tile = x - xr * ((S + 3) / 4);
+                int a, b, q;
+                gtd_locate(n, t, xr, &a, &b, &q);
+                const int sz = b - a;
+                const int r0 = 4 * tile;
+                if (sz < 2 || r0 >= sz) continue;
+                const int m = sz / 2, c = xr - a;
+                const double* Y = s.A + (size_t)a * S;
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                const int r1 = min(r0 + 4, sz);
                 for (int u = 0; u < r1 - r0; ++u) {
                     const int r = r0 + u;
                     const int c0 = r >= m ? m : 0, c1 = r >= m ? sz : m;
                     for (int col = c0; col < c1; ++col)
                         acc[u] = fma(Qc[(size_t)(a + col) * n + a + r], Y[(size_t)s.ip[a + col] * sz + c], acc[u]);
                 }
+                double* out = Qn + (size_t)(a + s.fp[a + c]) * n + a;
+                for (int u = 0; u < r1 - r0; ++u) out[r0 + u] = acc[u];
             }
-            double* out = Qn + (size_t)(a + s.fp[a + c]) * n + a;
-            for (int u = 0; u < r1 - r0; ++u) out[r0 + u] = acc[u];
         }
         __syncthreads();
         for (int x = tid; x < n; x += GTD_NT) {
@@ -661,32 +714,60 @@ __global__ __launch_bounds__(GTD_NT) void gtd_eig_kernel(GtdDesc g) {
         Qc = Qn;
         Qn = sw;
     }
-    // ---- 3. back-transformation: V^T = Z^T P^T, the reflectors applied to the
-    // rows of Z^T (= Qc) from the right, last reflector first
-    for (int i = grp; i < n; i += GTD_NT / 16)
-        for (int j = gl; j < n; j += 16) A[i * ld + j] = Qc[(size_t)i * n + j];
+    // ---- 3. back-transformation: V^T = Z^T P^T.  Each row of Z^T (= Qc, an
+    // eigenvector in the tridiagonal basis) takes the reflectors from the
+    // right, last first, independently of the other rows: a 16-lane group
+    // keeps two rows in registers (8 elements per lane) and reads the
+    // reflectors from LDS, so no barrier is needed between reflectors.
+    // the reflectors of the reduction: saved to global memory before divide
+    // and conquer took the LDS (rows with tau = 0 are never read)
+    for (int k = grp; k + 2 < n; k += GTD_NT / 16)
+        if (s.tau[k] != 0.0)
+            for (int j = gl; j < n; j += 16) A[k * ld + j] = g.refl[(size_t)k * n + j];
     __syncthreads();
-    for (int k = n - 3; k >= 0; --k) {
-        const double tk = s.tau[k];
-        if (tk == 0.0) continue;  // uniform
-        const int m = n - k - 1;
-        const double* v = g.refl + (size_t)k * n + k + 1;
-        for (int c = grp; c < n; c += GTD_NT / 16) {
-            double acc = 0.0;
-            for (int i = gl; i < m; i += 16) acc = fma(A[c * ld + k + 1 + i], v[i], acc);
-            acc = sum16(acc);
-            if (gl == 0) s.pp[c] = tk * acc;
+    constexpr int BE = GTD_MAX_N / 16;
+    for (int c0 = 2 * grp; c0 < n; c0 += 2 * (GTD_NT / 16)) {
+        const int c1 = c0 + 1;
+        double x0[BE], x1[BE];
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int j = gl + 16 * e;
+            x0[e] = j < n ? Qc[(size_t)c0 * n + j] : 0.0;
+            x1[e] = (j < n && c1 < n) ? Qc[(size_t)c1 * n + j] : 0.0;
         }
-        __syncthreads();
-        for (int c = grp; c < n; c += GTD_NT / 16) {
-            const double pc = s.pp[c];
-            double* row = A + c * ld + k + 1;
-            for (int i = gl; i < m; i += 16) row[i] -= pc * v[i];
+        for (int k = n - 3; k >= 0; --k) {
+            const double tk = s.tau[k];
+            if (tk == 0.0) continue;  // uniform
+            const double* v = A + k * ld;  // zero at columns <= k
+            const int e0 = (k + 1) >> 4;   // elements below e0 are at columns <= k for every lane
+            double vr[BE];
+#pragma unroll
+            for (int e = 0; e < BE; ++e) vr[e] = (e >= e0 && gl + 16 * e < n) ? v[gl + 16 * e] : 0.0;
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int e = 0; e < BE; ++e)
+                if (e >= e0) {
+                    d0 = fma(x0[e], vr[e], d0);
+                    d1 = fma(x1[e], vr[e], d1);
+                }
+            d0 = sum16(d0) * tk;
+            d1 = sum16(d1) * tk;
+#pragma unroll
+            for (int e = 0; e < BE; ++e)
+                if (e >= e0) {
+                    x0[e] = fma(-d0, vr[e], x0[e]);
+                    x1[e] = fma(-d1, vr[e], x1[e]);
+                }
         }
-        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int j = gl + 16 * e;
+            if (j < n) {
+                g.Vt[(size_t)c0 * n + j] = x0[e];
+                if (c1 < n) g.Vt[(size_t)c1 * n + j] = x1[e];
+            }
+        }
     }
-    for (int i = grp; i < n; i += GTD_NT / 16)
-        for (int j = gl; j < n; j += 16) g.Vt[(size_t)i * n + j] = A[i * ld + j];
 }
 
 // select + write: rows of W = V^T X^T (norm = s_i), descending order, the
