@@ -998,7 +998,7 @@ def main():
                 "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": measured_traffic(os.path.join(ROOT, "profiles", "jacobi_lds_bulk_n20_chi64_traffic.txt"),
                                             [os.path.join(ROOT, "paper_2601_16734_amd", "csrc", x)
-                                             for x in ("jacobi.hip", "select.h")]),
+                                             for x in ("jacobi.hip", "select.h", "rules.h")]),
                 "flops_per_launch": bulk_flops, "avg_launch_ms": f["bulk_split_ms_avg"],
                 "launches_per_step": f["bulk_splits_per_step"],
                 "share_of_step": f["factorization_ms_per_step"] / f["ms_per_step"],

@@ -444,6 +444,8 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
                                            zero_floor2(s_total2, nv, len, d.floor_eps), len, JAC_MAX_SWEEPS, Jw,
                                            nv);
     if (tid == 0 && d.log_sweeps) *d.log_sweeps = nsw;
+    // still rotating when the sweep budget ran out: reported like the blocked paths
+    if (tid == 0 && d.status && jacobi_unconverged(nsw, JAC_MAX_SWEEPS)) atomicOr(d.status, 2);
     const int r = jacobi_select(W, nv, len, ld, sig_raw, sig_sorted, perm, d, &s_delta);
     jacobi_write_rows(W, nv, len, ld, sig_sorted, perm, r, d.Q, d.basis, d.gram, Jw);
     if (ACC && d.acc_tag) {

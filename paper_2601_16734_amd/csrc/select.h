@@ -7,17 +7,9 @@
 #include <cfloat>
 
 #include "common.h"
+#include "rules.h"
 
 namespace smps {
-
-// Numerical rank floor: a vector whose norm is at most
-// u * max(nvec, len) * ||X||_F, with u the unit roundoff of the arithmetic that
-// produced X, is rounding noise of a rank-deficient matrix; it takes part in
-// no rotation and counts as a zero singular value.
-__device__ __forceinline__ double zero_floor2(double total2, int nv, int len, double u) {
-    const double f = u * (double)(nv > len ? nv : len);
-    return f * f * total2;
-}
 
 // Cross-lane move inside a row of 16 lanes (DPP), for a double.
 template <int CTRL>
@@ -81,51 +73,15 @@ static __device__ int jacobi_select(const double* W, int nv, int len, int ld, do
     __syncthreads();
     __shared__ int s_r;
     if (tid == 0) {
-        // weight not represented by the computed values (zero unless an exact
-        // total is supplied), counted in every tail
-        double all = 0.0;
-        for (int j = nv - 1; j >= 0; --j) all += sig_sorted[j] * sig_sorted[j];
-        const double total = d.total_ext ? *d.total_ext : all;
-        const double missed = d.total_ext ? fmax(0.0, total - all) : 0.0;
-        int r;
-        if (d.mode == SMPS_TRUNC_REL_SV) {
-            r = 0;
-            const double thr = d.tol * sig_sorted[0];
-            for (int j = 0; j < nv; ++j) r += sig_sorted[j] > thr;
-        } else {
-            // smallest r >= 1 whose tail (summed from the smallest value up) fits
-            const double thr = d.tol * total;
-            double t = missed;
-            int cand = nv;
-            if (t <= thr) {
-                while (cand > 1) {
-                    const double tn = t + sig_sorted[cand - 1] * sig_sorted[cand - 1];
-                    if (tn <= thr) {
-                        t = tn;
-                        --cand;
-                    } else {
-                        break;
-                    }
-                }
-            }
-            r = cand;
-        }
-        if (r < 1) r = 1;
-        if (r > d.max_rank) r = d.max_rank;
-        if (r > nv) r = nv;
-        if (r > len) r = len;
-        double delta = 0.0;
-        for (int j = nv - 1; j >= r; --j) delta += sig_sorted[j] * sig_sorted[j];
-        delta += missed;
+        // rank rule and weights (rules.h); with an exact total supplied, the
+        // weight the computed values miss is counted in every tail
+        const TruncResult tr = trunc_rule(sig_sorted, nv, len, d.mode, d.tol, d.max_rank, d.total_ext);
+        const int r = tr.r;
         s_r = r;
-        *s_delta = delta;
-        if (d.log_delta) *d.log_delta = delta;
+        *s_delta = tr.delta;
+        if (d.log_delta) *d.log_delta = tr.delta;
         if (d.log_rank) *d.log_rank = r;
-        if (d.log_norm2) {
-            double kept = 0.0;
-            for (int j = r - 1; j >= 0; --j) kept += sig_sorted[j] * sig_sorted[j];
-            *d.log_norm2 = kept;
-        }
+        if (d.log_norm2) *d.log_norm2 = tr.kept;
         d.dims_out[d.rank_idx] = r;
     }
     __syncthreads();
