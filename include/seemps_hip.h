@@ -21,6 +21,12 @@
  *     Calls that return host values (scalars, shapes, reads) synchronise
  *     that stream before returning.
  *   - One context must not be used from two host threads at once.
+ *   - Handles are checked on entry: NULL, a destroyed handle (or a pointer the
+ *     library never returned) and a handle of another context are refused
+ *     with SMPS_EINVAL, and destroying such a pointer returns SMPS_EINVAL.
+ *     (A new handle can reuse a destroyed one's address; the check cannot
+ *     tell those apart.)  Destroying a context destroys the handles it still
+ *     owns.
  */
 #ifndef SEEMPS_HIP_H
 #define SEEMPS_HIP_H
@@ -41,7 +47,8 @@ typedef enum {
     SMPS_ENOMEM = -2,       /* device allocation failed or a workspace limit was exceeded */
     SMPS_EHIP = -3,         /* a HIP runtime call failed */
     SMPS_ENUMERIC = -4,     /* non-finite values met in a factorization */
-    SMPS_EUNSUPPORTED = -5  /* valid request the library does not handle */
+    SMPS_EUNSUPPORTED = -5, /* valid request the library does not handle */
+    SMPS_ENODEV = -6        /* the call needs a device and the context is a planning context */
 } smps_status;
 
 /* storage type of host data handed to *_create */
@@ -118,10 +125,20 @@ typedef struct {
  * stream) on which all work of this context is enqueued; the caller keeps it
  * alive for the lifetime of the context. */
 int smps_ctx_create(int device, void *hip_stream, smps_ctx **out);
+/* A planning context: no device is used, so it works on a host without a GPU.
+ * Handles made in it hold shapes only (tensor data are not read), argument
+ * validation and smps_plan_apply / smps_plan_apply_batched work, and every
+ * call that would compute, read or copy device data returns SMPS_ENODEV
+ * after its arguments have been validated. */
+int smps_ctx_create_planning(smps_ctx **out);
 int smps_ctx_destroy(smps_ctx *ctx);
 const char *smps_last_error(const smps_ctx *ctx);
 /* Bytes of device workspace the context currently holds (grow-only arena). */
 int smps_ctx_workspace_bytes(const smps_ctx *ctx, size_t *bytes);
+/* Upper bound on the workspace arena, in bytes (0 = none, the default).  A
+ * call whose workspace would exceed it fails with SMPS_ENOMEM before any
+ * device work; an arena already above a new limit is released. */
+int smps_ctx_set_workspace_limit(smps_ctx *ctx, size_t bytes);
 /* Exact split of a two-site tensor in the single-problem sweep (Sec. 2.3):
  *   SMPS_SPLIT_AUTO (default): the method measured fastest for the size --
  *     at present the one-sided Jacobi SVD for every size;
@@ -296,6 +313,28 @@ int smps_dmrg(smps_ctx *ctx, const smps_mpo *H, const smps_mps *guess, const smp
    out[i] as for smps_mpo_apply; trunc_err (nullable) has n entries. */
 int smps_mpo_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
                            const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+
+/* ---- planning (host only) ------------------------------------------------------
+ * What smps_mpo_apply (one problem) or smps_mpo_apply_batched (n problems)
+ * would allocate and enqueue for these handles and strategy (Sec. 2.5
+ * sweep), computed on the host: nothing is allocated on or sent to a device,
+ * in either kind of context.  Same validation and the same refusals as the
+ * apply: SMPS_EUNSUPPORTED for two-site tensors beyond 2048 rows or columns
+ * and for a batch whose graph would exceed the kernel limit, SMPS_ENOMEM for
+ * a workspace above the context's limit; *info is filled before such a
+ * refusal, so the sizes that caused it can be read. */
+typedef struct {
+    size_t workspace_bytes;  /* device workspace of the call */
+    long long steps;         /* two-site updates, summed over the problems */
+    long long operations;    /* operations of the recorded sequence(s) */
+    long long launches;      /* batched: merged launches; single problem: = operations */
+    long long graph_kernels; /* batched: kernels the captured graph holds (upper bound); else 0 */
+    size_t descriptor_bytes; /* batched: descriptor arrays uploaded with the graph; else 0 */
+} smps_plan_info;
+int smps_plan_apply(smps_ctx *ctx, const smps_mpo *U, const smps_mps *v, const smps_strategy *strategy,
+                    smps_plan_info *info);
+int smps_plan_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
+                            const smps_strategy *strategy, smps_plan_info *info);
 
 /* ---- scalar product and norm (Sec. 2.4.4) -------------------------------------
  * scprod: <a, b> by the transfer-matrix sweep, O(L chi^3 d), FP64.

@@ -16,7 +16,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libseemps_hip.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED, ENODEV = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "bf16": PREC_BF16}
@@ -26,13 +26,15 @@ MLP_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + 64 + 1
 
 # every symbol the header declares, in declaration order
 EXPORTS = [
-    "smps_ctx_create", "smps_ctx_destroy", "smps_last_error", "smps_ctx_workspace_bytes", "smps_ctx_set_split",
+    "smps_ctx_create", "smps_ctx_create_planning", "smps_ctx_destroy", "smps_last_error",
+    "smps_ctx_workspace_bytes", "smps_ctx_set_workspace_limit", "smps_ctx_set_split",
     "smps_ctx_set_profiling",
     "smps_ctx_kernel_time",
     "smps_mps_create", "smps_mps_create_device", "smps_mps_destroy", "smps_mps_shape", "smps_mps_read",
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
     "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_transpose",
-    "smps_mpo_apply_right", "smps_mpo_list_apply", "smps_mpo_simplify", "smps_mpo_shape", "smps_mpo_read", "smps_mpo_apply_batched", "smps_scprod", "smps_norm",
+    "smps_mpo_apply_right", "smps_mpo_list_apply", "smps_mpo_simplify", "smps_mpo_shape", "smps_mpo_read",
+    "smps_mpo_apply_batched", "smps_plan_apply", "smps_plan_apply_batched", "smps_scprod", "smps_norm",
     "smps_scprod_noalloc",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
@@ -54,10 +56,20 @@ class ApplyInfo(ctypes.Structure):
                 ("reserved", c_int)]
 
 
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("workspace_bytes", c_size_t), ("steps", ctypes.c_longlong), ("operations", ctypes.c_longlong),
+                ("launches", ctypes.c_longlong), ("graph_kernels", ctypes.c_longlong),
+                ("descriptor_bytes", c_size_t)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SmpsError(RuntimeError):
-    def __init__(self, code: int, msg: str):
+    def __init__(self, code: int, msg: str, info: dict | None = None):
         super().__init__(f"[{code}] {msg}")
         self.code = code
+        self.info = info
 
 
 _lib = None
@@ -75,6 +87,11 @@ def load(path: str | None = None) -> ctypes.CDLL:
     vp, ip, dp = c_void_p, POINTER(c_int), POINTER(c_double)
     sig = {
         "smps_ctx_create": (c_int, [c_int, vp, POINTER(vp)]),
+        "smps_ctx_create_planning": (c_int, [POINTER(vp)]),
+        "smps_ctx_set_workspace_limit": (c_int, [vp, c_size_t]),
+        "smps_plan_apply": (c_int, [vp, vp, vp, POINTER(Strategy), POINTER(PlanInfo)]),
+        "smps_plan_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy),
+                                            POINTER(PlanInfo)]),
         "smps_ctx_destroy": (c_int, [vp]),
         "smps_last_error": (ctypes.c_char_p, [vp]),
         "smps_ctx_workspace_bytes": (c_int, [vp, POINTER(c_size_t)]),
@@ -297,10 +314,19 @@ class ZMPO:
 
 class Context:
     """A library context bound to one device and one HIP stream (torch's
-    current stream by default)."""
+    current stream by default), or a planning context (Context.planning())
+    with no device."""
 
-    def __init__(self, device: int = 0, stream: int | None = None):
+    def __init__(self, device: int = 0, stream: int | None = None, *, _planning: bool = False):
         self.lib = load()
+        if _planning:
+            h = c_void_p()
+            rc = self.lib.smps_ctx_create_planning(byref(h))
+            if rc != OK:
+                raise SmpsError(rc, "smps_ctx_create_planning failed")
+            self.h = h
+            self.device = -1
+            return
         if stream is None:
             import torch
             torch.cuda.set_device(device)
@@ -311,6 +337,11 @@ class Context:
             raise SmpsError(rc, f"smps_ctx_create(device={device}) failed")
         self.h = h
         self.device = device
+
+    @classmethod
+    def planning(cls) -> "Context":
+        """Context with no device: shapes, validation and planning only."""
+        return cls(_planning=True)
 
     def _check(self, rc: int):
         if rc != OK:
@@ -332,6 +363,23 @@ class Context:
         self._check(self.lib.smps_mps_create(self.h, L, phys, bonds, F64 if dtype == np.float64 else F32, ptrs,
                                              byref(h)))
         return MPS(self, h)
+
+    def mps_zeros(self, phys, bonds) -> MPS:
+        """MPS of the given shape with zero tensors (no host data passed); in a
+        planning context a shape-only handle."""
+        L = len(phys)
+        h = c_void_p()
+        self._check(self.lib.smps_mps_create(self.h, L, (c_int * L)(*phys), (c_int * (L + 1))(*bonds), F64, None,
+                                             byref(h)))
+        return MPS(self, h)
+
+    def mpo_zeros(self, pout, pin, bonds) -> MPO:
+        """MPO of the given shape with zero tensors; shape-only in a planning context."""
+        L = len(pout)
+        h = c_void_p()
+        self._check(self.lib.smps_mpo_create(self.h, L, (c_int * L)(*pout), (c_int * L)(*pin),
+                                             (c_int * (L + 1))(*bonds), F64, None, byref(h)))
+        return MPO(self, h, L)
 
     def mps_create_device(self, tensors) -> MPS:
         """From torch device tensors (float64 or float32), copied on the stream."""
@@ -518,6 +566,29 @@ class Context:
     def set_split(self, method: str) -> None:
         """'auto' (the library's choice), 'jacobi' or 'gram' (Gram / tridiagonal split for short vectors)."""
         self._check(self.lib.smps_ctx_set_split(self.h, {"auto": 0, "jacobi": 1, "gram": 2}[method]))
+
+    def set_workspace_limit(self, nbytes: int) -> None:
+        """Upper bound on the workspace arena (0: none); larger calls fail with ENOMEM."""
+        self._check(self.lib.smps_ctx_set_workspace_limit(self.h, int(nbytes)))
+
+    def plan_apply(self, U: MPO, v: MPS, st: Strategy) -> dict:
+        """What mpo_apply would allocate and enqueue (host only).  On a refusal
+        the SmpsError carries the filled sizes in .info."""
+        info = PlanInfo()
+        rc = self.lib.smps_plan_apply(self.h, U.h, v.h, byref(st), byref(info))
+        if rc != OK:
+            raise SmpsError(rc, self.lib.smps_last_error(self.h).decode(), info.as_dict())
+        return info.as_dict()
+
+    def plan_apply_batched(self, Us, vs, st: Strategy) -> dict:
+        n = len(vs)
+        uh = (c_void_p * n)(*[u.h for u in Us])
+        vh = (c_void_p * n)(*[v.h for v in vs])
+        info = PlanInfo()
+        rc = self.lib.smps_plan_apply_batched(self.h, n, uh, vh, byref(st), byref(info))
+        if rc != OK:
+            raise SmpsError(rc, self.lib.smps_last_error(self.h).decode(), info.as_dict())
+        return info.as_dict()
 
     def workspace_bytes(self) -> int:
         b = c_size_t()

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 
 #include "runtime.h"
 
@@ -13,8 +14,64 @@ int fail(smps_ctx* c, int code, const std::string& msg) {
     return code;
 }
 
+int need_device(smps_ctx* c) {
+    if (c->planning) return fail(c, SMPS_ENODEV, "a planning context has no device; this call needs one");
+    return SMPS_OK;
+}
+
+// ---- live handles
+namespace {
+struct LiveEntry {
+    smps_ctx* ctx;
+    int (*destroy)(void*);
+};
+std::mutex live_mu;
+std::unordered_map<const void*, LiveEntry>& live_handles() {
+    static std::unordered_map<const void*, LiveEntry> m;
+    return m;
+}
+}  // namespace
+
+void handle_track(const void* h, smps_ctx* c, int (*destroy)(void*)) {
+    std::lock_guard<std::mutex> g(live_mu);
+    live_handles()[h] = LiveEntry{c, destroy};
+}
+
+bool handle_untrack(const void* h) {
+    std::lock_guard<std::mutex> g(live_mu);
+    return live_handles().erase(h) == 1;
+}
+
+bool handle_live(const void* h) {
+    std::lock_guard<std::mutex> g(live_mu);
+    return live_handles().count(h) != 0;
+}
+
+int check_live(smps_ctx* c, const void* h, const smps_ctx* owner, const char* what) {
+    if (!h) return fail(c, SMPS_EINVAL, std::string("NULL ") + what + " handle");
+    if (!handle_live(h))
+        return fail(c, SMPS_EINVAL, std::string(what) + " handle is not live (destroyed, or not made by this library)");
+    if (c && owner != c) return fail(c, SMPS_EINVAL, std::string(what) + " handle belongs to another context");
+    return SMPS_OK;
+}
+
+int check_mps(smps_ctx* c, const smps_mps* m) {
+    if (!m || !handle_live(m)) return check_live(c, m, nullptr, "MPS");
+    return check_live(c, m, m->ctx, "MPS");
+}
+
+int check_mpo(smps_ctx* c, const smps_mpo* u) {
+    if (!u || !handle_live(u)) return check_live(c, u, nullptr, "MPO");
+    return check_live(c, u, u->ctx, "MPO");
+}
+
 void* dev_alloc(smps_ctx* c, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (c->planning) {
+        const uintptr_t a = PLAN_ADDRESS_BASE + c->plan_next;
+        c->plan_next += (bytes + 255) / 256 * 256;
+        return (void*)a;
+    }
     auto it = c->pool.find(bytes);
     if (it != c->pool.end()) {
         void* p = it->second;
@@ -27,18 +84,31 @@ void* dev_alloc(smps_ctx* c, size_t bytes) {
 }
 
 void dev_release(smps_ctx* c, void* p, size_t bytes) {
-    if (!p) return;
+    if (!p || c->planning) return;
     if (bytes == 0) bytes = 8;
     c->pool.emplace(bytes, p);
 }
 
+int check_workspace_limit(smps_ctx* c, size_t bytes) {
+    if (c->workspace_limit && bytes > c->workspace_limit)
+        return fail(c, SMPS_ENOMEM, "the call needs " + std::to_string(bytes) +
+                                        " bytes of workspace, above the context's limit of " +
+                                        std::to_string(c->workspace_limit) + " bytes");
+    return SMPS_OK;
+}
+
 int ensure_arena(smps_ctx* c, size_t bytes) {
+    int rc = check_workspace_limit(c, bytes);
+    if (rc) return rc;
     if (bytes <= c->arena_bytes) return SMPS_OK;
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     if (c->arena) hipFree(c->arena);
     c->arena = nullptr;
     c->arena_bytes = 0;
     size_t want = bytes + bytes / 8;
+    if (c->workspace_limit) want = std::min(want, c->workspace_limit);
     if (hipMalloc((void**)&c->arena, want) != hipSuccess) {
         c->arena = nullptr;
         return fail(c, SMPS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
@@ -92,6 +162,9 @@ void prof_collect(smps_ctx* c) {
     c->ev_used = 0;
 }
 
+static int destroy_mps_entry(void* h) { return smps_mps_destroy((smps_mps*)h); }
+static int destroy_mpo_entry(void* h) { return smps_mpo_destroy((smps_mpo*)h); }
+
 smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds) {
     smps_mps* m = new smps_mps();
     m->ctx = c;
@@ -110,7 +183,34 @@ smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::v
         delete m;
         return nullptr;
     }
+    handle_track(m, c, destroy_mps_entry);
     return m;
+}
+
+smps_mpo* new_mpo(smps_ctx* c, int L, const std::vector<int>& pout, const std::vector<int>& pin,
+                  const std::vector<int>& bonds, bool alloc) {
+    smps_mpo* u = new smps_mpo();
+    u->ctx = c;
+    u->L = L;
+    u->pout = pout;
+    u->pin = pin;
+    u->bonds = bonds;
+    u->off.resize(L);
+    size_t tot = 0;
+    for (int k = 0; k < L; ++k) {
+        u->off[k] = tot;
+        tot += u->site_size(k);
+    }
+    u->bytes = 8 * tot;
+    if (alloc) {
+        u->data = (double*)dev_alloc(c, u->bytes);
+        if (!u->data) {
+            delete u;
+            return nullptr;
+        }
+    }
+    handle_track(u, c, destroy_mpo_entry);
+    return u;
 }
 
 static int check_strategy(smps_ctx* c, const smps_strategy* st) {
@@ -191,8 +291,29 @@ int smps_ctx_create(int device, void* hip_stream, smps_ctx** out) {
     return SMPS_OK;
 }
 
+int smps_ctx_create_planning(smps_ctx** out) {
+    if (!out) return SMPS_EINVAL;
+    smps_ctx* c = new smps_ctx();
+    c->device = -1;
+    c->planning = true;
+    *out = c;
+    return SMPS_OK;
+}
+
 int smps_ctx_destroy(smps_ctx* c) {
     if (!c) return SMPS_EINVAL;
+    // the handles this context still owns go first (their storage returns to the pool)
+    std::vector<std::pair<void*, int (*)(void*)>> owned;
+    {
+        std::lock_guard<std::mutex> g(live_mu);
+        for (auto& kv : live_handles())
+            if (kv.second.ctx == c) owned.emplace_back(const_cast<void*>(kv.first), kv.second.destroy);
+    }
+    for (auto& h : owned) h.second(h.first);
+    if (c->planning) {
+        delete c;
+        return SMPS_OK;
+    }
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     if (c->arena) hipFree(c->arena);
@@ -210,6 +331,8 @@ const char* smps_last_error(const smps_ctx* c) { return c ? c->err.c_str() : "co
 
 int smps_ctx_set_profiling(smps_ctx* c, int on) {
     if (!c) return SMPS_EINVAL;
+    int rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
     c->profiling = on != 0;
@@ -222,6 +345,8 @@ int smps_ctx_set_profiling(smps_ctx* c, int on) {
 
 int smps_ctx_kernel_time(smps_ctx* c, int category, double* total_ms, long long* launches) {
     if (!c || category < 0 || category > 2) return SMPS_EINVAL;
+    int rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
     if (total_ms) *total_ms = c->prof_ms[category];
@@ -243,6 +368,20 @@ int smps_ctx_workspace_bytes(const smps_ctx* c, size_t* bytes) {
     return SMPS_OK;
 }
 
+int smps_ctx_set_workspace_limit(smps_ctx* c, size_t bytes) {
+    if (!c) return SMPS_EINVAL;
+    c->workspace_limit = bytes;
+    if (bytes && c->arena_bytes > bytes) {
+        SMPS_HIP(c, hipStreamSynchronize(c->stream));
+        SMPS_HIP(c, hipFree(c->arena));
+        c->arena = nullptr;
+        c->arena_bytes = 0;
+        // a cached batch graph addresses the old arena
+        batch_cache_free(c);
+    }
+    return SMPS_OK;
+}
+
 static int mps_create_impl(smps_ctx* c, int L, const int* phys, const int* bonds, int dtype,
                            const void* const* tensors, smps_mps** out, bool device) {
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
@@ -251,9 +390,17 @@ static int mps_create_impl(smps_ctx* c, int L, const int* phys, const int* bonds
     int rc = check_chain(c, L, phys, bonds);
     if (rc) return rc;
     if (dtype != SMPS_F64 && dtype != SMPS_F32) return fail(c, SMPS_EINVAL, "unknown dtype");
-    SMPS_HIP(c, hipSetDevice(c->device));
+    if (device || !c->planning) {
+        rc = need_device(c);
+        if (rc) return rc;
+        SMPS_HIP(c, hipSetDevice(c->device));
+    }
     smps_mps* m = new_mps(c, L, std::vector<int>(phys, phys + L), std::vector<int>(bonds, bonds + L + 1));
     if (!m) return fail(c, SMPS_ENOMEM, "MPS allocation failed");
+    if (c->planning) {  // shapes only
+        *out = m;
+        return SMPS_OK;
+    }
     std::vector<double> tmp;
     for (int k = 0; k < L; ++k) {
         const size_t n = m->site_size(k);
@@ -303,7 +450,7 @@ int smps_mps_create_device(smps_ctx* c, int L, const int* phys, const int* bonds
 }
 
 int smps_mps_destroy(smps_mps* m) {
-    if (!m) return SMPS_EINVAL;
+    if (!m || !handle_untrack(m)) return SMPS_EINVAL;
     if (m->ctx) dev_release(m->ctx, m->data, m->bytes);
     m->data = nullptr;
     delete m;
@@ -311,7 +458,7 @@ int smps_mps_destroy(smps_mps* m) {
 }
 
 int smps_mps_shape(const smps_mps* m, int* L, int* phys, int* bonds, int* center) {
-    if (!m) return SMPS_EINVAL;
+    if (!m || !handle_live(m)) return SMPS_EINVAL;
     if (L) *L = m->L;
     if (phys) std::memcpy(phys, m->phys.data(), sizeof(int) * m->L);
     if (bonds) std::memcpy(bonds, m->bonds.data(), sizeof(int) * (m->L + 1));
@@ -321,9 +468,13 @@ int smps_mps_shape(const smps_mps* m, int* L, int* phys, int* bonds, int* center
 
 int smps_mps_read(smps_ctx* c, const smps_mps* m, int site, double* host_out, size_t count) {
     if (!c) return SMPS_EINVAL;
-    if (!m || !host_out) return fail(c, SMPS_EINVAL, "NULL argument");
+    int rc = check_mps(c, m);
+    if (rc) return rc;
+    if (!host_out) return fail(c, SMPS_EINVAL, "NULL argument");
     if (site < 0 || site >= m->L) return fail(c, SMPS_EINVAL, "site out of range");
     if (count != m->site_size(site)) return fail(c, SMPS_EINVAL, "count does not match the site size");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     SMPS_HIP(c, hipMemcpyAsync(host_out, m->data + m->off[site], 8 * count, hipMemcpyDeviceToHost, c->stream));
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
@@ -331,7 +482,7 @@ int smps_mps_read(smps_ctx* c, const smps_mps* m, int site, double* host_out, si
 }
 
 int smps_mpo_shape(const smps_mpo* u, int* L, int* pout, int* pin, int* bonds) {
-    if (!u) return SMPS_EINVAL;
+    if (!u || !handle_live(u)) return SMPS_EINVAL;
     if (L) *L = u->L;
     if (pout) std::memcpy(pout, u->pout.data(), sizeof(int) * u->L);
     if (pin) std::memcpy(pin, u->pin.data(), sizeof(int) * u->L);
@@ -341,9 +492,13 @@ int smps_mpo_shape(const smps_mpo* u, int* L, int* pout, int* pin, int* bonds) {
 
 int smps_mpo_read(smps_ctx* c, const smps_mpo* u, int site, double* host_out, size_t count) {
     if (!c) return SMPS_EINVAL;
-    if (!u || !host_out) return fail(c, SMPS_EINVAL, "NULL argument");
+    int rc = check_mpo(c, u);
+    if (rc) return rc;
+    if (!host_out) return fail(c, SMPS_EINVAL, "NULL argument");
     if (site < 0 || site >= u->L) return fail(c, SMPS_EINVAL, "site out of range");
     if (count != u->site_size(site)) return fail(c, SMPS_EINVAL, "count does not match the site size");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     SMPS_HIP(c, hipMemcpyAsync(host_out, u->data + u->off[site], 8 * count, hipMemcpyDeviceToHost, c->stream));
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
@@ -351,7 +506,8 @@ int smps_mpo_read(smps_ctx* c, const smps_mpo* u, int site, double* host_out, si
 }
 
 int smps_mps_device_ptr(const smps_mps* m, int site, const double** ptr) {
-    if (!m || !ptr || site < 0 || site >= m->L) return SMPS_EINVAL;
+    if (!m || !handle_live(m) || !ptr || site < 0 || site >= m->L) return SMPS_EINVAL;
+    if (m->ctx->planning) return SMPS_ENODEV;
     *ptr = m->data + m->off[site];
     return SMPS_OK;
 }
@@ -366,25 +522,15 @@ int smps_mpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const i
     rc = check_chain(c, L, pin, bonds);
     if (rc) return rc;
     if (dtype != SMPS_F64 && dtype != SMPS_F32) return fail(c, SMPS_EINVAL, "unknown dtype");
-    SMPS_HIP(c, hipSetDevice(c->device));
-    smps_mpo* u = new smps_mpo();
-    u->ctx = c;
-    u->L = L;
-    u->pout.assign(pout, pout + L);
-    u->pin.assign(pin, pin + L);
-    u->bonds.assign(bonds, bonds + L + 1);
-    u->off.resize(L);
-    size_t tot = 0;
-    for (int k = 0; k < L; ++k) {
-        u->off[k] = tot;
-        tot += u->site_size(k);
+    if (!c->planning) SMPS_HIP(c, hipSetDevice(c->device));
+    smps_mpo* u = new_mpo(c, L, std::vector<int>(pout, pout + L), std::vector<int>(pin, pin + L),
+                          std::vector<int>(bonds, bonds + L + 1));
+    if (!u) return fail(c, SMPS_ENOMEM, "MPO allocation failed");
+    if (c->planning) {  // shapes only
+        *out = u;
+        return SMPS_OK;
     }
-    u->bytes = 8 * tot;
-    u->data = (double*)dev_alloc(c, u->bytes);
-    if (!u->data) {
-        delete u;
-        return fail(c, SMPS_ENOMEM, "MPO allocation failed");
-    }
+    const size_t tot = u->bytes / 8;
     std::vector<double> h(tot, 0.0);
     for (int k = 0; k < L; ++k) {
         const void* src = tensors ? tensors[k] : nullptr;
@@ -406,14 +552,17 @@ int smps_mpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const i
 }
 
 int smps_mpo_destroy(smps_mpo* u) {
-    if (!u) return SMPS_EINVAL;
+    if (!u || !handle_untrack(u)) return SMPS_EINVAL;
     if (u->ctx) dev_release(u->ctx, u->data, u->bytes);
     delete u;
     return SMPS_OK;
 }
 
 static int check_pair(smps_ctx* c, const smps_mpo* U, const smps_mps* v) {
-    if (!U || !v) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_mpo(c, U);
+    if (rc) return rc;
+    rc = check_mps(c, v);
+    if (rc) return rc;
     if (U->L != v->L) return fail(c, SMPS_EINVAL, "MPO and MPS lengths differ");
     for (int k = 0; k < v->L; ++k)
         if (U->pin[k] != v->phys[k]) return fail(c, SMPS_EINVAL, "MPO input dimension differs from MPS physical dimension");
@@ -433,7 +582,9 @@ int smps_mpo_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps
     if (rc) return rc;
     rc = check_strategy(c, st);
     if (rc) return rc;
-    SMPS_HIP(c, hipSetDevice(c->device));
+    // a planning context gets as far as the workspace: SMPS_ENOMEM above its
+    // limit, else SMPS_ENODEV
+    if (!c->planning) SMPS_HIP(c, hipSetDevice(c->device));
     return run_apply(c, U, v, *st, out, trunc_err);
 }
 
@@ -441,8 +592,11 @@ int smps_simplify(smps_ctx* c, const smps_mps* v, const smps_strategy* st, smps_
     if (!c) return SMPS_EINVAL;
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!v) return fail(c, SMPS_EINVAL, "NULL handle");
-    int rc = check_strategy(c, st);
+    int rc = check_mps(c, v);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
+    if (rc) return rc;
+    rc = need_device(c);
     if (rc) return rc;
     // identity operator with bond 1 (Eq. simplification with phi = v)
     std::vector<int> bonds(v->L + 1, 1);
@@ -486,7 +640,8 @@ int smps_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, 
     int rc = check_strategy(c, st);
     if (rc) return rc;
     for (int i = 0; i < n; ++i) {
-        if (!v[i]) return fail(c, SMPS_EINVAL, "NULL state handle");
+        rc = check_mps(c, v[i]);
+        if (rc) return rc;
         if (!std::isfinite(w[i])) return fail(c, SMPS_EINVAL, "weights must be finite");
         if (v[i]->L != v[0]->L || v[i]->phys != v[0]->phys)
             return fail(c, SMPS_EINVAL, "the states of a combination must share length and physical dimensions");
@@ -495,6 +650,8 @@ int smps_combine(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, 
             if (rc) return rc;
         }
     }
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     std::vector<const smps_mpo*> ops(n);
     std::vector<smps_mpo*> owned;
@@ -519,21 +676,13 @@ int smps_mpo_transpose(smps_ctx* c, const smps_mpo* U, smps_mpo** out) {
     if (!c) return SMPS_EINVAL;
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!U) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_mpo(c, U);
+    if (rc) return rc;
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
-    smps_mpo* T = new smps_mpo();
-    T->ctx = c;
-    T->L = U->L;
-    T->pout = U->pin;
-    T->pin = U->pout;
-    T->bonds = U->bonds;
-    T->off = U->off;  // same site sizes
-    T->bytes = U->bytes;
-    T->data = (double*)dev_alloc(c, T->bytes);
-    if (!T->data) {
-        delete T;
-        return fail(c, SMPS_ENOMEM, "MPO allocation failed");
-    }
+    smps_mpo* T = new_mpo(c, U->L, U->pin, U->pout, U->bonds);  // same site sizes as U
+    if (!T) return fail(c, SMPS_ENOMEM, "MPO allocation failed");
     for (int k = 0; k < U->L; ++k) {
         const hipError_t e = launch_mpo_site_transpose(U->data + U->off[k], T->data + T->off[k], U->bonds[k],
                                                        U->pout[k], U->pin[k], U->bonds[k + 1], c->stream);
@@ -592,8 +741,11 @@ int smps_mpo_simplify(smps_ctx* c, const smps_mpo* U, const smps_strategy* st, s
     if (!c) return SMPS_EINVAL;
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!U) return fail(c, SMPS_EINVAL, "NULL handle");
-    int rc = check_strategy(c, st);
+    int rc = check_mpo(c, U);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
+    if (rc) return rc;
+    rc = need_device(c);
     if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     std::vector<int> phys(U->L);
@@ -605,15 +757,8 @@ int smps_mpo_simplify(smps_ctx* c, const smps_mpo* U, const smps_strategy* st, s
     rc = smps_simplify(c, m, st, &r, trunc_err);
     smps_mps_destroy(m);
     if (rc) return rc;
-    smps_mpo* T = new smps_mpo();
-    T->ctx = c;
-    T->L = U->L;
-    T->pout = U->pout;
-    T->pin = U->pin;
-    T->bonds = r->bonds;
-    T->off = r->off;
-    T->bytes = r->bytes;
-    T->data = r->data;  // the MPS storage becomes the operator's
+    smps_mpo* T = new_mpo(c, U->L, U->pout, U->pin, r->bonds, false);
+    T->data = r->data;  // the MPS storage becomes the operator's (same sizes and offsets)
     r->data = nullptr;
     r->bytes = 0;
     smps_mps_destroy(r);
@@ -626,8 +771,11 @@ int smps_dmrg(smps_ctx* c, const smps_mpo* H, const smps_mps* guess, const smps_
     if (!c) return SMPS_EINVAL;
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!H || !guess) return fail(c, SMPS_EINVAL, "NULL handle");
-    int rc = check_strategy(c, st);
+    int rc = check_mpo(c, H);
+    if (rc) return rc;
+    rc = check_mps(c, guess);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
     if (rc) return rc;
     if (st->precision != SMPS_PREC_FP64 || st->factorization != SMPS_FACT_SVD)
         return fail(c, SMPS_EUNSUPPORTED, "DMRG runs in FP64 with the exact factorization");
@@ -637,6 +785,8 @@ int smps_dmrg(smps_ctx* c, const smps_mpo* H, const smps_mps* guess, const smps_
     for (int k = 0; k < H->L; ++k)
         if (H->pout[k] != guess->phys[k] || H->pin[k] != guess->phys[k])
             return fail(c, SMPS_EINVAL, "operator site dimensions must equal the guess's");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     return run_dmrg(c, H, guess, *st, krylov_dim, out, energy);
 }
@@ -652,8 +802,35 @@ int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const s
         rc = check_pair(c, U[i], v[i]);
         if (rc) return rc;
     }
-    SMPS_HIP(c, hipSetDevice(c->device));
+    if (!c->planning) SMPS_HIP(c, hipSetDevice(c->device));
     return run_apply_batched(c, n, U, v, *st, out, trunc_err);
+}
+
+int smps_plan_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy* st,
+                    smps_plan_info* info) {
+    if (!c) return SMPS_EINVAL;
+    if (!info) return fail(c, SMPS_EINVAL, "info is NULL");
+    *info = smps_plan_info{};
+    int rc = check_pair(c, U, v);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
+    if (rc) return rc;
+    return plan_apply(c, 1, &U, &v, *st, false, info);
+}
+
+int smps_plan_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                            const smps_strategy* st, smps_plan_info* info) {
+    if (!c) return SMPS_EINVAL;
+    if (!info) return fail(c, SMPS_EINVAL, "info is NULL");
+    *info = smps_plan_info{};
+    if (n < 0 || (n > 0 && (!U || !v))) return fail(c, SMPS_EINVAL, "bad batch arguments");
+    int rc = check_strategy(c, st);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = check_pair(c, U[i], v[i]);
+        if (rc) return rc;
+    }
+    return plan_apply(c, n, U, v, *st, true, info);
 }
 
 int smps_last_info(const smps_ctx* c, smps_apply_info* info) {
@@ -676,10 +853,13 @@ int smps_last_log(const smps_ctx* c, int max_steps, double* deltas, int* ranks, 
 int smps_autotune_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy* st, int reps,
                         int* tuned) {
     if (!c) return SMPS_EINVAL;
-    if (!U || !v) return fail(c, SMPS_EINVAL, "NULL handle");
-    int rc = check_strategy(c, st);
+    int rc = check_pair(c, U, v);
+    if (rc) return rc;
+    rc = check_strategy(c, st);
     if (rc != SMPS_OK) return rc;
     if (reps < 1) return fail(c, SMPS_EINVAL, "reps must be >= 1");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     return run_autotune(c, U, v, *st, reps, tuned);
 }
@@ -708,11 +888,15 @@ int smps_last_factor_log(const smps_ctx* c, int max_steps, int* kinds, int* step
 namespace {
 
 int check_scprod_args(smps_ctx* c, const smps_mps* a, const smps_mps* b, const double* out) {
-    if (!a || !b || !out) return fail(c, SMPS_EINVAL, "NULL argument");
+    int rc = check_mps(c, a);
+    if (rc) return rc;
+    rc = check_mps(c, b);
+    if (rc) return rc;
+    if (!out) return fail(c, SMPS_EINVAL, "NULL argument");
     if (a->L != b->L) return fail(c, SMPS_EINVAL, "lengths differ");
     for (int k = 0; k < a->L; ++k)
         if (a->phys[k] != b->phys[k]) return fail(c, SMPS_EINVAL, "physical dimensions differ");
-    return SMPS_OK;
+    return need_device(c);
 }
 
 // Workspace of the transfer-matrix sweep: offsets of E0, E1 (largest
@@ -814,7 +998,11 @@ int smps_scprod_noalloc(smps_ctx* c, const smps_mps* a, const smps_mps* b, doubl
 
 int smps_norm(smps_ctx* c, const smps_mps* a, double* out) {
     if (!c) return SMPS_EINVAL;
-    if (!a || !out) return fail(c, SMPS_EINVAL, "NULL argument");
+    int rc0 = check_mps(c, a);
+    if (rc0) return rc0;
+    if (!out) return fail(c, SMPS_EINVAL, "NULL argument");
+    rc0 = need_device(c);
+    if (rc0) return rc0;
     if (a->center < 0) {
         double s = 0.0;
         int rc = smps_scprod(c, a, a, &s);

@@ -146,6 +146,7 @@ int smps_autotune_gemm(smps_ctx* c, int precision, int M, int N, int K, int ta, 
     if (precision < SMPS_PREC_FP64 || precision > SMPS_PREC_BF16) return fail(c, SMPS_EINVAL, "unknown precision");
     for (int t : {a_type, b_type, c_type})
         if (t != SMPS_F64 && t != SMPS_F32) return fail(c, SMPS_EINVAL, "unknown operand type");
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     return tune_gemm_shape(c, precision, a_type, b_type, c_type, ta != 0, tb != 0, tc != 0, M, N, K, reps, best_tile);
 }

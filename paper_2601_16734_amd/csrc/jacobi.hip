@@ -654,8 +654,14 @@ __global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d0, const JacobiDes
     }
 }
 
-// LDS a Jacobi workgroup may use: the device limit, capped at 160 KB.
-static int g_lds_bytes = 64 * 1024;
+// Dynamic LDS a Jacobi workgroup may use: the device limit, capped at the
+// gfx950 160 KB, less a fixed reserve for the kernels' static LDS (a few
+// scalars and at most SEL_MAX-sized arrays in the selection kernels, checked
+// at initialisation).  The value does not depend on anything but the limit,
+// so that a planning context (no device) takes the same path decisions as a
+// gfx950 device.
+constexpr int LDS_STATIC_RESERVE = 1024;
+static int g_lds_bytes = LDS_BYTES - LDS_STATIC_RESERVE;
 
 hipError_t jacobi_init(int device) {
     int lim = 0;
@@ -678,7 +684,7 @@ hipError_t jacobi_init(int device) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
     }
-    int dyn = lim - (int)((stat + 255) / 256 * 256);
+    int dyn = lim - std::max(LDS_STATIC_RESERVE, (int)((stat + 255) / 256 * 256));
     bool ok = true;
     for (const void* f : kernels)
         ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) == hipSuccess;

@@ -251,6 +251,7 @@ extern "C" {
 
 int smps_rank_mlp_init(smps_ctx* c, unsigned long long seed) {
     if (!c) return SMPS_EINVAL;
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     MlpState* s = state(c);
     int rc = ensure_data(c, s, 256);
@@ -274,6 +275,7 @@ int smps_rank_mlp_init(smps_ctx* c, unsigned long long seed) {
 
 int smps_rank_mlp_get(const smps_ctx* c, float* params, int count) {
     if (!c || !params || count != NPAR || !c->mlp || !((MlpState*)c->mlp)->init) return SMPS_EINVAL;
+    if (c->planning) return SMPS_ENODEV;
     MlpState* s = (MlpState*)c->mlp;
     if (hipMemcpy(params, s->params, sizeof(float) * NPAR, hipMemcpyDeviceToHost) != hipSuccess) return SMPS_EHIP;
     return SMPS_OK;
@@ -282,6 +284,7 @@ int smps_rank_mlp_get(const smps_ctx* c, float* params, int count) {
 int smps_rank_mlp_set(smps_ctx* c, const float* params, int count) {
     if (!c) return SMPS_EINVAL;
     if (!params || count != NPAR) return fail(c, SMPS_EINVAL, "expected 6337 parameters");
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     MlpState* s = state(c);
     int rc = ensure_data(c, s, 256);
@@ -310,6 +313,7 @@ int smps_rank_mlp_grad(smps_ctx* c, int n, const float* feats, const float* labe
         return fail(c, SMPS_EINVAL, "bad arguments to smps_rank_mlp_grad");
     MlpState* s = (MlpState*)c->mlp;
     if (!s || !s->init) return fail(c, SMPS_EINVAL, "rank predictor not initialised");
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     int rc = upload_set(c, s, n, feats, labels);
     if (rc) return rc;
@@ -329,6 +333,7 @@ int smps_rank_mlp_train(smps_ctx* c, int n, const float* feats, const float* lab
         return fail(c, SMPS_EINVAL, "bad arguments to smps_rank_mlp_train");
     MlpState* s = (MlpState*)c->mlp;
     if (!s || !s->init) return fail(c, SMPS_EINVAL, "rank predictor not initialised");
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     int rc = upload_set(c, s, n, feats, labels);
     if (rc) return rc;
@@ -412,6 +417,7 @@ int smps_rank_mlp_predict(smps_ctx* c, int n, const float* feats, float* out) {
     if (n < 1 || !feats || !out) return fail(c, SMPS_EINVAL, "bad arguments to smps_rank_mlp_predict");
     MlpState* s = (MlpState*)c->mlp;
     if (!s || !s->init) return fail(c, SMPS_EINVAL, "rank predictor not initialised");
+    if (int rc_dev = need_device(c)) return rc_dev;
     SMPS_HIP(c, hipSetDevice(c->device));
     int rc = upload_set(c, s, n, feats, nullptr);
     if (rc) return rc;

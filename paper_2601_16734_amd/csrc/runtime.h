@@ -9,6 +9,13 @@
 
 struct smps_ctx {
     int device = 0;
+    // a planning context (smps_ctx_create_planning) has no device: handles
+    // hold shapes and notional addresses, validation and the planning entry
+    // points work, nothing is allocated, copied or launched
+    bool planning = false;
+    size_t plan_next = 0;  // next notional address offset of a planning context
+    // largest workspace arena the context may hold, in bytes (0: no limit)
+    size_t workspace_limit = 0;
     hipStream_t stream = nullptr;
     std::string err;
     // grow-only workspace arena for apply/simplify/scprod
@@ -70,6 +77,24 @@ struct smps_mpo {
 
 namespace smps {
 int fail(smps_ctx* c, int code, const std::string& msg);
+// SMPS_ENODEV when c is a planning context (call before any device work)
+int need_device(smps_ctx* c);
+// SMPS_ENOMEM when a workspace of `bytes` exceeds the context's limit
+int check_workspace_limit(smps_ctx* c, size_t bytes);
+// Notional device addresses of a planning context and of planned workspaces:
+// distinct, aligned values above this base, so that recorded operations look
+// like real ones; nothing ever dereferences them.
+constexpr uintptr_t PLAN_ADDRESS_BASE = uintptr_t(1) << 44;
+// Live-handle registry: every handle the library hands out is registered
+// with its context and its destroy function until it is destroyed, so a
+// destroyed or foreign pointer is refused instead of dereferenced, and a
+// context destroys the handles it still owns.
+void handle_track(const void* h, smps_ctx* c, int (*destroy)(void*));
+bool handle_untrack(const void* h);  // false when h was not live
+bool handle_live(const void* h);
+int check_mps(smps_ctx* c, const smps_mps* m);  // non-NULL, live, owned by c
+int check_mpo(smps_ctx* c, const smps_mpo* u);
+int check_live(smps_ctx* c, const void* h, const smps_ctx* owner, const char* what);
 void* dev_alloc(smps_ctx* c, size_t bytes);
 void dev_release(smps_ctx* c, void* p, size_t bytes);
 int ensure_arena(smps_ctx* c, size_t bytes);
@@ -81,6 +106,9 @@ int prof_begin(smps_ctx* c, hipStream_t s);
 void prof_end(smps_ctx* c, hipStream_t s, int token, int category, int also = -1);
 void prof_collect(smps_ctx* c);
 smps_mps* new_mps(smps_ctx* c, int L, const std::vector<int>& phys, const std::vector<int>& bonds);
+// operator handle with offsets; device storage allocated when alloc is set
+smps_mpo* new_mpo(smps_ctx* c, int L, const std::vector<int>& pout, const std::vector<int>& pin,
+                  const std::vector<int>& bonds, bool alloc = true);
 
 // Enqueue one apply + compression and collect its results (used by the single
 // and the batched entry points).
@@ -107,6 +135,10 @@ bool mlp_ready(const smps_ctx* c);
 void batch_cache_free(smps_ctx* c);
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
                       const smps_strategy& st, smps_mps** out, double* trunc_err);
+// What an apply (n = 1) or a batched apply would allocate and enqueue; runs
+// on the host only (any context kind).
+int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v, const smps_strategy& st,
+               bool batched, smps_plan_info* info);
 }  // namespace smps
 
 #define SMPS_HIP(c, expr)                                                                         \

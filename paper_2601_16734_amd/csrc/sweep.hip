@@ -1004,10 +1004,9 @@ static int finish(smps_ctx* c, const Plan& p, const Enq& q, const smps_strategy&
 
 // One chain, one or several (weight, operator, state) terms; the first term's
 // state is the guess.
-static int run_terms(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
-                     const smps_strategy& st, smps_mps** out, double* trunc_err) {
-    Plan p;
-    Layout lay;
+// Plan of one chain (every term) with the workspace of the context's split.
+static int plan_single(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
+                       const smps_strategy& st, Plan& p, Layout& lay) {
     plan_problem(p, U[0], v[0], st, lay);
     if (p.max_nvec > 2048)
         return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
@@ -1018,7 +1017,16 @@ static int run_terms(smps_ctx* c, int n, const double* w, const smps_mpo* const*
         const int nc = std::min(p.max_nvec, 1024), lc = std::min(p.max_nvec, 128);
         if (gtd_supported(nc, lc)) p.o_gtd = lay.add(8 * gtd_work_doubles(nc, lc));
     }
-    int rc = ensure_arena(c, lay.total);
+    return SMPS_OK;
+}
+
+static int run_terms(smps_ctx* c, int n, const double* w, const smps_mpo* const* U, const smps_mps* const* v,
+                     const smps_strategy& st, smps_mps** out, double* trunc_err) {
+    Plan p;
+    Layout lay;
+    int rc = plan_single(c, n, w, U, v, st, p, lay);
+    if (rc != SMPS_OK) return rc;
+    rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     if (st.factorization == SMPS_FACT_RSVD_MLP && !mlp_ready(c))
         return fail(c, SMPS_EINVAL, "the randomized factorization sized by the rank predictor needs "
@@ -1405,20 +1413,122 @@ void batch_cache_free(smps_ctx* c) {
     c->batch = nullptr;
 }
 
-int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                      const smps_strategy& st, smps_mps** out, double* trunc_err) {
+// Plans of all problems of a batch in one workspace.
+static int plan_batch(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                      const smps_strategy& st, std::vector<Plan>& plans, Layout& lay) {
     if (st.factorization != SMPS_FACT_SVD)
         return fail(c, SMPS_EUNSUPPORTED, "the batched path uses the exact factorization only");
-    if (n == 0) return SMPS_OK;
-    // ---- plans of all problems in one workspace
-    std::vector<Plan> plans(n);
-    Layout lay;
+    plans.resize(n);
     for (int i = 0; i < n; ++i) {
         plan_problem(plans[i], U[i], v[i], st, lay);
         if (plans[i].max_nvec > 2048)
             return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
     }
-    int rc = ensure_arena(c, lay.total);
+    return SMPS_OK;
+}
+
+// Every problem's operation sequence recorded against the workspace at
+// `base`, merged into batched launches (descriptors staged in da); *nodes is
+// the kernel count of the graph that would hold them.  Host only.
+static int record_batch(smps_ctx* c, const std::vector<Plan>& plans, const smps_mpo* const* U,
+                        const smps_mps* const* v, const smps_strategy& st, char* base, DescArena& da,
+                        std::vector<Launch>& launches, long long* nodes, long long* nops) {
+    const int n = (int)plans.size();
+    std::vector<std::vector<Op>> ops(n);
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        Enq q{plans[i], U[i], v[i], st, base, c->stream, (int*)(base + plans[i].o_dims)};
+        q.rec = &ops[i];
+        hipError_t e = q.run();
+        if (e != hipSuccess) return fail(c, SMPS_EHIP, std::string("recording failed at ") + q.where);
+        total += (long long)ops[i].size();
+    }
+    build_launches(ops, da, launches);
+    *nodes = graph_kernels(launches);
+    if (nops) *nops = total;
+    return SMPS_OK;
+}
+
+static int refuse_graph(smps_ctx* c, long long nodes) {
+    return fail(c, SMPS_EUNSUPPORTED,
+                "the batch would capture " + std::to_string(nodes) + " kernels (limit " +
+                    std::to_string(MAX_GRAPH_KERNELS) +
+                    "); chains whose two-site tensors exceed the LDS by far take the single-problem path");
+}
+
+// Gather descriptors of the per-problem results (addresses in the workspace at
+// `base`) appended to da, followed by the results area of `stride` doubles
+// per problem.
+struct GatherLayout {
+    size_t gd_off = 0, res_off = 0, stride = 0;
+};
+static GatherLayout append_gather(const std::vector<Plan>& plans, char* base, DescArena& da) {
+    const int n = (int)plans.size();
+    GatherLayout g;
+    for (int i = 0; i < n; ++i) g.stride = std::max(g.stride, (size_t)(4 + plans[i].L + 1));
+    std::vector<GatherDesc> gd(n);
+    for (int i = 0; i < n; ++i) {
+        const Plan& p = plans[i];
+        gd[i] = GatherDesc{(const int*)(base + p.o_dims), p.L, (const int*)(base + p.o_status),
+                           (const double*)(base + p.o_norm2), (const double*)(base + p.o_ldelta), p.steps, nullptr};
+    }
+    g.gd_off = da.add(gd.data(), sizeof(GatherDesc) * n);
+    g.res_off = (da.host.size() + 63) / 64 * 64;
+    da.host.resize(g.res_off + sizeof(double) * g.stride * n);
+    return g;
+}
+
+int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v, const smps_strategy& st,
+               bool batched, smps_plan_info* info) {
+    char* const base = (char*)PLAN_ADDRESS_BASE;  // notional workspace: recorded, never dereferenced
+    if (!batched) {
+        Plan p;
+        Layout lay;
+        const double one = 1.0;
+        int rc = plan_single(c, 1, &one, U, v, st, p, lay);
+        if (rc != SMPS_OK) return rc;
+        info->workspace_bytes = lay.total;
+        info->steps = p.steps;
+        std::vector<Op> ops;
+        Enq q{p, U[0], v[0], st, base, c->stream, (int*)(base + p.o_dims)};
+        q.rec = &ops;
+        if (q.run() != hipSuccess) return fail(c, SMPS_EHIP, std::string("planning: recording failed at ") + q.where);
+        info->operations = info->launches = (long long)ops.size();
+        return check_workspace_limit(c, lay.total);
+    }
+    if (n == 0) return SMPS_OK;
+    std::vector<Plan> plans;
+    Layout lay;
+    int rc = plan_batch(c, n, U, v, st, plans, lay);
+    if (rc != SMPS_OK) return rc;
+    info->workspace_bytes = lay.total;
+    for (const Plan& p : plans) info->steps += p.steps;
+    DescArena da;
+    std::vector<Launch> launches;
+    long long nodes = 0, nops = 0;
+    rc = record_batch(c, plans, U, v, st, base, da, launches, &nodes, &nops);
+    if (rc != SMPS_OK) return rc;
+    append_gather(plans, base, da);
+    info->operations = nops;
+    info->launches = (long long)launches.size();
+    info->graph_kernels = nodes;
+    info->descriptor_bytes = da.host.size();
+    rc = check_workspace_limit(c, lay.total);
+    if (rc != SMPS_OK) return rc;
+    return nodes > MAX_GRAPH_KERNELS ? refuse_graph(c, nodes) : SMPS_OK;
+}
+
+int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                      const smps_strategy& st, smps_mps** out, double* trunc_err) {
+    if (n == 0) return st.factorization == SMPS_FACT_SVD
+                           ? SMPS_OK
+                           : fail(c, SMPS_EUNSUPPORTED, "the batched path uses the exact factorization only");
+    // ---- plans of all problems in one workspace
+    std::vector<Plan> plans;
+    Layout lay;
+    int rc = plan_batch(c, n, U, v, st, plans, lay);
+    if (rc != SMPS_OK) return rc;
+    rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
     // cache key: the handles, their data, the workspace and the strategy
     std::vector<const void*> key;
@@ -1438,37 +1548,18 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
         bc = new BatchCache();
         c->batch = bc;
         // ---- record every problem's operation sequence
-        std::vector<std::vector<Op>> ops(n);
-        for (int i = 0; i < n; ++i) {
-            Enq q{plans[i], U[i], v[i], st, c->arena, c->stream, (int*)(c->arena + plans[i].o_dims)};
-            q.rec = &ops[i];
-            hipError_t e = q.run();
-            if (e != hipSuccess) return fail(c, SMPS_EHIP, std::string("recording failed: ") + hipGetErrorString(e));
-        }
         DescArena da;
         std::vector<Launch> launches;
-        build_launches(ops, da, launches);
-        const long long nodes = graph_kernels(launches);
-        if (nodes > MAX_GRAPH_KERNELS) {
+        long long nodes = 0;
+        rc = record_batch(c, plans, U, v, st, c->arena, da, launches, &nodes, nullptr);
+        if (rc == SMPS_OK && nodes > MAX_GRAPH_KERNELS) rc = refuse_graph(c, nodes);
+        if (rc != SMPS_OK) {
             batch_cache_free(c);
-            return fail(c, SMPS_EUNSUPPORTED,
-                        "the batch would capture " + std::to_string(nodes) + " kernels (limit " +
-                            std::to_string(MAX_GRAPH_KERNELS) +
-                            "); chains whose two-site tensors exceed the LDS by far take the single-problem path");
+            return rc;
         }
         // gather of the per-problem results into one buffer
-        size_t stride = 0;
-        for (int i = 0; i < n; ++i) stride = std::max(stride, (size_t)(4 + plans[i].L + 1));
-        std::vector<GatherDesc> gd(n);
-        for (int i = 0; i < n; ++i) {
-            const Plan& p = plans[i];
-            gd[i] = GatherDesc{(const int*)(c->arena + p.o_dims), p.L, (const int*)(c->arena + p.o_status),
-                               (const double*)(c->arena + p.o_norm2), (const double*)(c->arena + p.o_ldelta),
-                               p.steps, nullptr};
-        }
-        const size_t gd_off = da.add(gd.data(), sizeof(GatherDesc) * n);
-        const size_t res_off = (da.host.size() + 63) / 64 * 64;
-        da.host.resize(res_off + sizeof(double) * stride * n);
+        const GatherLayout gl = append_gather(plans, c->arena, da);
+        const size_t gd_off = gl.gd_off, res_off = gl.res_off, stride = gl.stride;
         // device copy of the descriptors (results area follows them)
         SMPS_HIP(c, hipMalloc((void**)&bc->desc_dev, da.host.size()));
         bc->desc_bytes = da.host.size();

@@ -43,6 +43,22 @@ struct smps_zmpo {
 };
 
 namespace smps {
+
+// complex handles, registered like the real ones (see runtime.h)
+static int destroy_zmps_entry(void* h) { return smps_zmps_destroy((smps_zmps*)h); }
+static int destroy_zmpo_entry(void* h) { return smps_zmpo_destroy((smps_zmpo*)h); }
+static smps_zmps* new_zmps_handle(smps_ctx* c) {
+    smps_zmps* m = new smps_zmps();
+    m->ctx = c;
+    handle_track(m, c, destroy_zmps_entry);
+    return m;
+}
+static smps_zmpo* new_zmpo_handle(smps_ctx* c) {
+    smps_zmpo* m = new smps_zmpo();
+    m->ctx = c;
+    handle_track(m, c, destroy_zmpo_entry);
+    return m;
+}
 namespace {
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
@@ -625,7 +641,7 @@ struct ZApply {
             }
         }
         // result handle
-        smps_zmps* res = new smps_zmps();
+        smps_zmps* res = new_zmps_handle(c);
         res->ctx = c;
         res->L = L;
         res->phys = d;
@@ -640,6 +656,7 @@ struct ZApply {
         res->bytes = sizeof(double2) * std::max<size_t>(tot, 1);
         res->data = (double2*)dev_alloc(c, res->bytes);
         if (!res->data) {
+            handle_untrack(res);
             delete res;
             return fail(c, SMPS_ENOMEM, "output allocation failed");
         }
@@ -689,9 +706,10 @@ int smps_zmps_create(smps_ctx* c, int L, const int* phys, const int* bonds, cons
     int rc = zcheck_chain(c, L, phys, bonds);
     if (rc) return rc;
     if (!tensors) return fail(c, SMPS_EINVAL, "tensors is NULL");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
-    smps_zmps* m = new smps_zmps();
-    m->ctx = c;
+    smps_zmps* m = new_zmps_handle(c);
     m->L = L;
     m->phys.assign(phys, phys + L);
     m->bonds.assign(bonds, bonds + L + 1);
@@ -704,12 +722,14 @@ int smps_zmps_create(smps_ctx* c, int L, const int* phys, const int* bonds, cons
     m->bytes = sizeof(double2) * std::max<size_t>(tot, 1);
     m->data = (double2*)dev_alloc(c, m->bytes);
     if (!m->data) {
+        handle_untrack(m);
         delete m;
         return fail(c, SMPS_ENOMEM, "allocation failed");
     }
     for (int k = 0; k < L; ++k) {
         if (!tensors[k]) {
             dev_release(c, m->data, m->bytes);
+            handle_untrack(m);
             delete m;
             return fail(c, SMPS_EINVAL, "site tensor is NULL");
         }
@@ -717,6 +737,7 @@ int smps_zmps_create(smps_ctx* c, int L, const int* phys, const int* bonds, cons
                                        hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             dev_release(c, m->data, m->bytes);
+            handle_untrack(m);
             delete m;
             return fail(c, SMPS_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
         }
@@ -727,13 +748,14 @@ int smps_zmps_create(smps_ctx* c, int L, const int* phys, const int* bonds, cons
 
 int smps_zmps_destroy(smps_zmps* m) {
     if (!m) return SMPS_OK;
+    if (!handle_untrack(m)) return SMPS_EINVAL;
     if (m->data) dev_release(m->ctx, m->data, m->bytes);
     delete m;
     return SMPS_OK;
 }
 
 int smps_zmps_shape(const smps_zmps* m, int* L, int* phys, int* bonds) {
-    if (!m) return SMPS_EINVAL;
+    if (!m || !handle_live(m)) return SMPS_EINVAL;
     if (L) *L = m->L;
     if (phys) std::copy(m->phys.begin(), m->phys.end(), phys);
     if (bonds) std::copy(m->bonds.begin(), m->bonds.end(), bonds);
@@ -742,9 +764,13 @@ int smps_zmps_shape(const smps_zmps* m, int* L, int* phys, int* bonds) {
 
 int smps_zmps_read(smps_ctx* c, const smps_zmps* m, int site, double* host_out, size_t count) {
     if (!c) return SMPS_EINVAL;
-    if (!m || !host_out) return fail(c, SMPS_EINVAL, "NULL argument");
+    int rc = check_live(c, m, m && handle_live(m) ? m->ctx : nullptr, "complex MPS");
+    if (rc) return rc;
+    if (!host_out) return fail(c, SMPS_EINVAL, "NULL argument");
     if (site < 0 || site >= m->L) return fail(c, SMPS_EINVAL, "site out of range");
     if (count != m->site_size(site)) return fail(c, SMPS_EINVAL, "count does not match the site size");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     SMPS_HIP(c, hipMemcpy(host_out, m->data + m->off[site], sizeof(double2) * count, hipMemcpyDeviceToHost));
@@ -761,9 +787,10 @@ int smps_zmpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const 
     rc = zcheck_chain(c, L, pin, bonds);
     if (rc) return rc;
     if (!tensors) return fail(c, SMPS_EINVAL, "tensors is NULL");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
-    smps_zmpo* m = new smps_zmpo();
-    m->ctx = c;
+    smps_zmpo* m = new_zmpo_handle(c);
     m->L = L;
     m->pout.assign(pout, pout + L);
     m->pin.assign(pin, pin + L);
@@ -777,12 +804,14 @@ int smps_zmpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const 
     m->bytes = sizeof(double2) * std::max<size_t>(tot, 1);
     m->data = (double2*)dev_alloc(c, m->bytes);
     if (!m->data) {
+        handle_untrack(m);
         delete m;
         return fail(c, SMPS_ENOMEM, "allocation failed");
     }
     for (int k = 0; k < L; ++k) {
         if (!tensors[k]) {
             dev_release(c, m->data, m->bytes);
+            handle_untrack(m);
             delete m;
             return fail(c, SMPS_EINVAL, "site tensor is NULL");
         }
@@ -790,6 +819,7 @@ int smps_zmpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const 
                                        hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             dev_release(c, m->data, m->bytes);
+            handle_untrack(m);
             delete m;
             return fail(c, SMPS_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
         }
@@ -800,6 +830,7 @@ int smps_zmpo_create(smps_ctx* c, int L, const int* pout, const int* pin, const 
 
 int smps_zmpo_destroy(smps_zmpo* m) {
     if (!m) return SMPS_OK;
+    if (!handle_untrack(m)) return SMPS_EINVAL;
     if (m->data) dev_release(m->ctx, m->data, m->bytes);
     delete m;
     return SMPS_OK;
@@ -810,7 +841,10 @@ int smps_zmpo_apply(smps_ctx* c, const smps_zmpo* U, const smps_zmps* v, const s
     if (!c) return SMPS_EINVAL;
     if (!out) return fail(c, SMPS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!U || !v) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_live(c, U, U && handle_live(U) ? U->ctx : nullptr, "complex MPO");
+    if (rc) return rc;
+    rc = check_live(c, v, v && handle_live(v) ? v->ctx : nullptr, "complex MPS");
+    if (rc) return rc;
     if (!st) return fail(c, SMPS_EINVAL, "strategy is NULL");
     if (st->max_bond < 1 || !(st->tol >= 0.0) || !std::isfinite(st->tol) || st->max_sweeps < 1)
         return fail(c, SMPS_EINVAL, "bad strategy");
@@ -822,6 +856,8 @@ int smps_zmpo_apply(smps_ctx* c, const smps_zmpo* U, const smps_zmps* v, const s
     for (int k = 0; k < v->L; ++k)
         if (U->pin[k] != v->phys[k] || U->pout[k] != v->phys[k])
             return fail(c, SMPS_EUNSUPPORTED, "complex apply needs square operator sites matching the state");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     ZApply za(c, U, v, *st);
     return za.run(out, trunc_err);
@@ -830,8 +866,13 @@ int smps_zmpo_apply(smps_ctx* c, const smps_zmpo* U, const smps_zmps* v, const s
 // <a, b> = sum conj(a) b by the transfer-matrix sweep (Sec. 2.4.4)
 int smps_zscprod(smps_ctx* c, const smps_zmps* a, const smps_zmps* b, double* re, double* im) {
     if (!c) return SMPS_EINVAL;
-    if (!a || !b) return fail(c, SMPS_EINVAL, "NULL handle");
+    int rc = check_live(c, a, a && handle_live(a) ? a->ctx : nullptr, "complex MPS");
+    if (rc) return rc;
+    rc = check_live(c, b, b && handle_live(b) ? b->ctx : nullptr, "complex MPS");
+    if (rc) return rc;
     if (a->L != b->L || a->phys != b->phys) return fail(c, SMPS_EINVAL, "shapes do not match");
+    rc = need_device(c);
+    if (rc) return rc;
     SMPS_HIP(c, hipSetDevice(c->device));
     const int L = a->L;
     size_t ne = 1, nt = 1;

@@ -1,0 +1,288 @@
+"""The C ABI on a host without a GPU: argument validation, handle checks,
+workspace limits and planning, in a planning context (no device).
+
+Two builds run the same calls: the library as built (through the binding),
+and the library built with the host code under the address and
+undefined-behaviour sanitizers, driven by tests/host/abi_check.cpp -- which
+also records the batched launch sequence of one L=100, chi=256 chain (the
+capture that exceeds the graph kernel limit) and of the 512-chain QTT batch,
+so that the recording, the launch merging and the kernel count run under
+the sanitizers."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2601_16734_amd import binding as B
+
+MAX_GRAPH_KERNELS = 100000  # the batched path's capture limit
+
+
+@pytest.fixture
+def pctx():
+    c = B.Context.planning()
+    yield c
+    c.close()
+
+
+def chain_shapes(L, d, chi, D):
+    bonds = synth.bond_caps(L, d, chi)
+    return [d] * L, bonds, [d] * L, [d] * L, [1] + [D] * (L - 1) + [1]
+
+
+def make(ctx, L, d, chi, D):
+    phys, bonds, pout, pin, ob = chain_shapes(L, d, chi, D)
+    return ctx.mpo_zeros(pout, pin, ob), ctx.mps_zeros(phys, bonds)
+
+
+def code_of(fn, *a):
+    with pytest.raises(B.SmpsError) as e:
+        fn(*a)
+    return e.value.code, str(e.value)
+
+
+# ---------------------------------------------------------------- contexts and handles
+
+def test_null_context_and_null_arguments():
+    lib = B.load()
+    st = B.strategy(8, 1e-10)
+    out = B.c_void_p()
+    err = B.c_double()
+    assert lib.smps_mpo_apply(None, None, None, B.byref(st), B.byref(out), B.byref(err)) == B.EINVAL
+    assert lib.smps_plan_apply(None, None, None, B.byref(st), None) == B.EINVAL
+    assert lib.smps_ctx_create_planning(None) == B.EINVAL
+    assert lib.smps_ctx_destroy(None) == B.EINVAL
+    assert lib.smps_mps_destroy(None) == B.EINVAL
+    assert lib.smps_mpo_destroy(None) == B.EINVAL
+    assert lib.smps_last_error(None) == b"context is NULL"
+    assert lib.smps_ctx_set_workspace_limit(None, 0) == B.EINVAL
+
+
+def test_planning_handles_carry_shapes_and_refuse_device_work(pctx):
+    U, v = make(pctx, 10, 2, 8, 3)
+    phys, bonds, centre = v.shape()
+    assert phys == [2] * 10 and bonds == synth.bond_caps(10, 2, 8) and centre == -1
+    assert U.shape()[2] == [1] + [3] * 9 + [1]
+    assert code_of(v.read)[0] == B.ENODEV
+    assert code_of(U.read)[0] == B.ENODEV
+    assert code_of(v.device_ptr, 0)[0] == B.ENODEV
+    assert code_of(pctx.scprod, v, v)[0] == B.ENODEV
+    assert code_of(pctx.norm, v)[0] == B.ENODEV
+    assert code_of(pctx.mpo_transpose, U)[0] == B.ENODEV
+    assert code_of(pctx.simplify, v, B.strategy(8, 1e-10))[0] == B.ENODEV
+    # validated, planned, then refused for want of a device
+    code, msg = code_of(pctx.mpo_apply, U, v, B.strategy(8, 1e-10))
+    assert code == B.ENODEV and "planning context" in msg
+    assert code_of(pctx.mpo_apply_batched, [U], [v], B.strategy(8, 1e-10))[0] == B.ENODEV
+
+
+def test_destroyed_foreign_and_orphaned_handles(pctx):
+    lib = B.load()
+    U, v = make(pctx, 8, 2, 4, 2)
+    raw = v.h
+    assert lib.smps_mps_destroy(raw) == B.OK
+    v.h = raw  # keep the stale pointer
+    code, msg = code_of(pctx.mpo_apply, U, v, B.strategy(4, 1e-10))
+    assert code == B.EINVAL and "not live" in msg
+    code, msg = code_of(pctx.plan_apply, U, v, B.strategy(4, 1e-10))
+    assert code == B.EINVAL and "not live" in msg
+    assert lib.smps_mps_shape(raw, None, None, None, None) == B.EINVAL
+    assert lib.smps_mps_destroy(raw) == B.EINVAL  # second destroy
+    v.h = None
+    # a handle of another context
+    other = B.Context.planning()
+    U2, v2 = make(other, 8, 2, 4, 2)
+    code, msg = code_of(pctx.mpo_apply, U, v2, B.strategy(4, 1e-10))
+    assert code == B.EINVAL and "another context" in msg
+    # destroying a context destroys the handles it still owns
+    h_u2, h_v2 = U2.h, v2.h
+    other.close()
+    assert lib.smps_mps_destroy(h_v2) == B.EINVAL
+    assert lib.smps_mpo_destroy(h_u2) == B.EINVAL
+    U2.h = v2.h = None
+
+
+@pytest.mark.parametrize("field,value", [("max_bond", 0), ("max_bond", -3), ("tol", -1e-12), ("tol", math.nan),
+                                         ("tol", math.inf), ("max_sweeps", 0), ("trunc_mode", 7),
+                                         ("precision", 9), ("factorization", 11)])
+def test_strategy_is_validated_without_a_device(pctx, field, value):
+    U, v = make(pctx, 12, 2, 16, 3)
+    st = B.strategy(16, 1e-10)
+    setattr(st, field, value)
+    for fn in (pctx.mpo_apply, pctx.plan_apply):
+        assert code_of(fn, U, v, st)[0] == B.EINVAL
+    assert code_of(pctx.mpo_apply_batched, [U], [v], st)[0] == B.EINVAL
+    assert code_of(pctx.plan_apply_batched, [U], [v], st)[0] == B.EINVAL
+
+
+def test_shapes_are_validated_without_a_device(pctx):
+    lib = B.load()
+    h = B.c_void_p()
+    ints = lambda *x: (B.c_int * len(x))(*x)  # noqa: E731
+    # open ends must be 1, dimensions >= 1, L >= 1
+    assert lib.smps_mps_create(pctx.h, 2, ints(2, 2), ints(2, 2, 1), B.F64, None, B.byref(h)) == B.EINVAL
+    assert lib.smps_mps_create(pctx.h, 2, ints(2, 0), ints(1, 2, 1), B.F64, None, B.byref(h)) == B.EINVAL
+    assert lib.smps_mps_create(pctx.h, 0, ints(2), ints(1), B.F64, None, B.byref(h)) == B.EINVAL
+    assert lib.smps_mps_create(pctx.h, 2, ints(2, 2), ints(1, 2, 1), 5, None, B.byref(h)) == B.EINVAL
+    st = B.strategy(8, 1e-10)
+    U, v = make(pctx, 8, 2, 8, 2)
+    U9, _ = make(pctx, 9, 2, 8, 2)
+    assert code_of(pctx.mpo_apply, U9, v, st)[0] == B.EINVAL  # lengths differ
+    U3 = pctx.mpo_zeros([3] * 8, [3] * 8, [1] + [2] * 7 + [1])
+    assert code_of(pctx.mpo_apply, U3, v, st)[0] == B.EINVAL  # input dimension != physical dimension
+    Urect = pctx.mpo_zeros([3] * 8, [2] * 8, [1] + [2] * 7 + [1])
+    assert code_of(pctx.mpo_apply, Urect, v, st)[0] == B.EUNSUPPORTED  # the guess needs d_out == d_in
+    st_r = B.strategy(8, 1e-10, factorization=B.FACT_RSVD_PREV)
+    assert code_of(pctx.plan_apply_batched, [U], [v], st_r)[0] == B.EUNSUPPORTED
+
+
+# ---------------------------------------------------------------- workspace limit and planning
+
+def test_workspace_limit_refuses_before_device_work(pctx):
+    U, v = make(pctx, 20, 2, 64, 8)
+    st = B.strategy(64, 1e-10)
+    need = pctx.plan_apply(U, v, st)["workspace_bytes"]
+    assert need > 0
+    pctx.set_workspace_limit(need - 1)
+    code, msg = code_of(pctx.plan_apply, U, v, st)
+    assert code == B.ENOMEM and str(need) in msg
+    code, msg = code_of(pctx.mpo_apply, U, v, st)
+    assert code == B.ENOMEM and "limit" in msg
+    assert code_of(pctx.mpo_apply_batched, [U], [v], st)[0] == B.ENOMEM
+    pctx.set_workspace_limit(need)
+    assert code_of(pctx.mpo_apply, U, v, st)[0] == B.ENODEV  # within the limit: only the device is missing
+    pctx.set_workspace_limit(0)
+    assert pctx.plan_apply(U, v, st)["workspace_bytes"] == need
+
+
+@pytest.mark.parametrize("L,chi,D,sweeps", [(20, 64, 8, 4), (100, 256, 5, 4), (64, 512, 8, 4), (10, 8, 3, 1)])
+def test_plan_follows_the_sweep(pctx, L, chi, D, sweeps):
+    U, v = make(pctx, L, 2, chi, D)
+    info = pctx.plan_apply(U, v, B.strategy(chi, 1e-10, sweeps=sweeps))
+    # one two-site update per bond and direction per sweep (Sec. 2.5)
+    assert info["steps"] == 2 * sweeps * (L - 1)
+    # the two-site tensor of the widest bond alone: (d chi)^2 doubles
+    assert info["workspace_bytes"] >= 8 * (2 * chi) ** 2
+    assert info["operations"] >= info["steps"] and info["graph_kernels"] == 0
+
+
+def test_batched_plan_counts_the_graph_and_refuses_beyond_the_limit(pctx):
+    st = B.strategy(256, 1e-10, sweeps=4)
+    U, v = make(pctx, 100, 2, 256, 5)
+    code, msg = code_of(pctx.plan_apply_batched, [U], [v], st)
+    assert code == B.EUNSUPPORTED and "kernels" in msg
+    with pytest.raises(B.SmpsError) as e:
+        pctx.plan_apply_batched([U], [v], st)
+    assert e.value.info["graph_kernels"] > MAX_GRAPH_KERNELS
+    assert e.value.info["steps"] == 2 * 4 * 99
+
+
+def batch_groups(ctx):
+    groups = {}
+    for w in synth.workload_batch(0):
+        phys = [t.shape[1] for t in w.mps]
+        bonds = [t.shape[0] for t in w.mps] + [1]
+        ob = [t.shape[0] for t in w.mpo] + [1]
+        groups.setdefault(w.max_bond, []).append((ctx.mpo_zeros(phys, phys, ob), ctx.mps_zeros(phys, bonds)))
+    return groups
+
+
+def test_the_512_chain_batch_plans_within_the_graph_limit(pctx):
+    total_steps = 0
+    for chi, pairs in sorted(batch_groups(pctx).items()):
+        info = pctx.plan_apply_batched([p[0] for p in pairs], [p[1] for p in pairs],
+                                       B.strategy(chi, 1e-10, sweeps=4))
+        assert 0 < info["graph_kernels"] <= MAX_GRAPH_KERNELS, (chi, info)
+        assert info["launches"] <= info["operations"]
+        total_steps += info["steps"]
+    assert total_steps == sum(8 * (w.meta["n"] - 1) for w in synth.workload_batch(0))
+
+
+# ---------------------------------------------------------------- the sanitized build
+
+def strategy_line(max_bond, tol=1e-10, mode=0, sweeps=4, prec=0, fact=0):
+    return f"{max_bond} {tol!r} {mode} {sweeps} {prec} {fact}"
+
+
+class Script:
+    def __init__(self):
+        self.lines, self.n_mps, self.n_mpo = [], 0, 0
+
+    def ctx(self):
+        self.lines.append("ctx")
+
+    def chain(self, c, phys, bonds, pout, pin, ob):
+        L = len(phys)
+        self.lines.append(f"mpo {c} {L} {' '.join(map(str, pout))} {' '.join(map(str, pin))} "
+                          f"{' '.join(map(str, ob))}")
+        self.lines.append(f"mps {c} {L} {' '.join(map(str, phys))} {' '.join(map(str, bonds))}")
+        self.n_mpo += 1
+        self.n_mps += 1
+        return self.n_mpo - 1, self.n_mps - 1
+
+
+@pytest.fixture(scope="module")
+def abi_exe():
+    from tests.host import sanitized_build
+    try:
+        return sanitized_build.build_abi_check()
+    except RuntimeError as e:
+        pytest.fail(f"sanitized build failed: {e}")
+
+
+def test_sanitized_build_drives_validation_planning_and_batched_recording(abi_exe):
+    from tests.host import sanitized_build
+    s = Script()
+    s.ctx()
+    s.ctx()
+    u_small, v_small = s.chain(0, *chain_shapes(20, 2, 64, 8))
+    u_big, v_big = s.chain(0, *chain_shapes(100, 2, 256, 5))
+    _, v_other = s.chain(1, *chain_shapes(20, 2, 64, 8))
+    groups = {}
+    for w in synth.workload_batch(0):
+        phys = [t.shape[1] for t in w.mps]
+        bonds = [t.shape[0] for t in w.mps] + [1]
+        ob = [t.shape[0] for t in w.mpo] + [1]
+        groups.setdefault(w.max_bond, []).append(s.chain(0, phys, bonds, phys, phys, ob))
+    n_setup = len(s.lines)
+    checks = []
+
+    def add(line, expect):
+        s.lines.append(line)
+        checks.append(expect)
+
+    add(f"plan 0 {u_small} {v_small} {strategy_line(64)}", ("rc", 0))
+    add(f"plan 0 {u_big} {v_big} {strategy_line(256)}", ("rc", 0))
+    add(f"planb 0 1 {u_big} {v_big} {strategy_line(256)}", ("big", B.EUNSUPPORTED))
+    for chi, pairs in sorted(groups.items()):
+        add(f"planb 0 {len(pairs)} {' '.join(f'{a} {b}' for a, b in pairs)} {strategy_line(chi)}", ("group", 0))
+    add(f"apply 0 {u_small} {v_small} {strategy_line(0)}", ("rc", B.EINVAL))
+    add(f"apply 0 {u_small} {v_small} {strategy_line(64, tol=-1.0)}", ("rc", B.EINVAL))
+    add(f"apply 0 {u_small} {v_small} {strategy_line(64)}", ("rc", B.ENODEV))
+    add(f"apply 0 {u_small} {v_other} {strategy_line(64)}", ("rc", B.EINVAL))
+    add(f"apply 0 -1 {v_small} {strategy_line(64)}", ("rc", B.EINVAL))
+    add(f"scprod 0 {v_small} {v_small}", ("rc", B.ENODEV))
+    add("limit 0 1000", ("rc", 0))
+    add(f"apply 0 {u_small} {v_small} {strategy_line(64)}", ("rc", B.ENOMEM))
+    add(f"plan 0 {u_small} {v_small} {strategy_line(64)}", ("rc", B.ENOMEM))
+    add("limit 0 0", ("rc", 0))
+    add(f"destroy_mps {v_small}", ("rc", 0))
+    add(f"destroy_mps {v_small}", ("rc", B.EINVAL))
+    add(f"shape_mps {v_small}", ("rc", B.EINVAL))
+    add(f"apply 0 {u_small} {v_small} {strategy_line(64)}", ("rc", B.EINVAL))
+    add(f"plan 0 {u_small} {v_small} {strategy_line(64)}", ("rc", B.EINVAL))
+    add("destroy_ctx 1", ("rc", 0))
+    add(f"destroy_mps {v_other}", ("rc", B.EINVAL))  # went with its context
+    out = sanitized_build.run_abi_check(abi_exe, "\n".join(s.lines) + "\n")
+    results = out[n_setup:]
+    assert all(line.split()[1] == "0" for line in out[:n_setup] if line.startswith("rc")), out[:n_setup]
+    assert len(results) == len(checks)
+    for line, (kind, rc) in zip(results, checks):
+        f = line.split()
+        assert int(f[1]) == rc, (line, kind)
+        if kind == "big":
+            assert int(f[6]) > MAX_GRAPH_KERNELS
+        if kind == "group":
+            assert 0 < int(f[6]) <= MAX_GRAPH_KERNELS

@@ -13,22 +13,13 @@ import pytest
 
 from oracle import mps as om
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_2601_16734_amd", "csrc")
-
 
 @pytest.fixture(scope="module")
 def rules_exe(tmp_path_factory):
-    cxx = shutil.which("g++")
-    if cxx is None:
+    if shutil.which("g++") is None:
         pytest.skip("no host C++ compiler")
-    out = str(tmp_path_factory.mktemp("rules") / "rules_check")
-    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-           "-I", CSRC, "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host", "rules_check.cpp"),
-           "-o", out]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr
-    return out
+    from tests.host import sanitized_build
+    return sanitized_build.build_rules_check(str(tmp_path_factory.mktemp("rules") / "rules_check"))
 
 
 def run_cases(exe, lines):
