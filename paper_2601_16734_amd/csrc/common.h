@@ -150,8 +150,26 @@ size_t jacobi_panel_bytes(int len_cap, int bs);
 // every descriptor of one launch has the same `accumulate` setting (acc)
 hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, size_t shm, hipStream_t s,
                                      bool acc = false);
-hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk, int max_rows,
-                                       int len_cap, size_t shm, int sweeps, hipStream_t s);
+// Queue state of one persistent batched blocked launch: the queue head and,
+// per team of workgroups, its barrier count, current factorization, a
+// give-up flag and the rotation flags of sweeps s mod 3 (one 128-byte line
+// each).  The launch zeroes it before the persistent kernel starts.
+struct PanelTeamState {
+    int bar, prob, abort, rot[3];
+    int pad[26];
+};
+constexpr int PANEL_MAX_TEAMS = 256;
+struct PanelQueueState {
+    int head;
+    int pad[31];
+    PanelTeamState team[PANEL_MAX_TEAMS];
+};
+constexpr size_t PANEL_QUEUE_BYTES = sizeof(PanelQueueState);
+// teams of a persistent launch of `count` factorizations of at most
+// max_pairs block pairs (grid = teams x max_pairs workgroups)
+int jacobi_panel_teams(int count, int max_pairs);
+hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_rows, int len_cap,
+                                       size_t shm, PanelQueueState* q, hipStream_t s);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
                                hipStream_t s, int prec);
 hipError_t launch_left_mpo_batched(const LeftMpoDesc* arr, int count, const LeftMpoDesc& types, int a_cap,

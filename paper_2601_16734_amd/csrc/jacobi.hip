@@ -461,27 +461,22 @@ __host__ __device__ constexpr int panel_threads(int E, int G) {
     return G == 64 ? 1024 : G == 32 ? 512 : lds_threads(E);
 }
 
-// One round of the blocked path: workgroup i takes the block pair of
-// tournament position i, orthogonalises the union in LDS, writes it back.
-// Rows are zero padded to G E elements (E > 0), E held per lane by groups of
-// G lanes; E = 0 is the strided generic loop.  Batched launches index the
-// factorization by blockIdx.y; a factorization whose `done` flag is set
-// (converged in an earlier sweep) exits at once.
-template <int E, int G = 16>
-__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_kernel(JacobiDesc d0, const JacobiDesc* arr,
-                                                                          int rd) {
+// One block pair of round rd of the blocked path: position `pos` of the
+// tournament over blocks, the union orthogonalised in LDS (one inner sweep)
+// and written back when it rotated.  Rows are zero padded to G E elements
+// (E > 0), E held per lane by groups of G lanes; E = 0 is the strided generic
+// loop.  Returns 1 when a rotation was applied, 0 otherwise, -1 on
+// non-finite input (status bit 1 set).  Uniform over the workgroup.
+template <int E, int G>
+__device__ int panel_pair_round(const JacobiDesc& d, int rd, int pos, double* sm, int* s_flag, int* s_bad,
+                                double* s_nrm) {
     constexpr int NT = panel_threads(E, G);
-    extern __shared__ double sm[];
-    __shared__ int s_flag, s_bad;
-    __shared__ double s_nrm[64];
-    const JacobiDesc d = arr ? arr[blockIdx.y] : d0;
     const int bs = d.bs, nblk2 = d.nblk;
-    if (rd >= nblk2 - 1 || (int)blockIdx.x >= nblk2 / 2) return;
-    if (d.done && *d.done) return;
+    if (rd >= nblk2 - 1 || pos >= nblk2 / 2) return 0;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     // rows zero padded to G E in LDS for the register path (E > 0)
     const int ld = E > 0 ? G * E : len;
-    const int bp = tourney(blockIdx.x, rd, nblk2), bq = tourney(nblk2 - 1 - blockIdx.x, rd, nblk2);
+    const int bp = tourney(pos, rd, nblk2), bq = tourney(nblk2 - 1 - pos, rd, nblk2);
     // vectors of the two blocks that exist
     int idx[2], cnt[2];
     idx[0] = bp * bs;
@@ -489,32 +484,163 @@ __global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_kernel(Jacob
     cnt[0] = min(bs, max(0, nv - idx[0]));
     cnt[1] = min(bs, max(0, nv - idx[1]));
     const int nloc = cnt[0] + cnt[1];
-    if (nloc < 2) return;
+    if (nloc < 2) return 0;
     const int tid = threadIdx.x;
-    if (tid == 0) s_bad = 0;
+    if (tid == 0) *s_bad = 0;
     __syncthreads();
     const double* X = d.X;
     const int i0 = idx[0], i1 = idx[1], c0 = cnt[0];
     const int bad = load_rows_to_lds(
         sm, nloc, len, ld, [=](int j) { return X + (size_t)(j < c0 ? i0 + j : i1 + (j - c0)) * len; }, tid, NT);
-    if (bad) s_bad = 1;
+    if (bad) *s_bad = 1;
     __syncthreads();
-    if (s_bad) {
-        if (tid == 0 && d.status) *d.status = 1;
-        return;
+    if (*s_bad) {
+        if (tid == 0 && d.status) atomicOr(d.status, 1);
+        return -1;
     }
     // one inner sweep per round: the outer tournament then acts as one cyclic ordering
-    const bool any = jacobi_orth_t<E, G>(sm, nloc, E > 0 ? ld : len, ld, s_nrm, &s_flag,
+    const bool any = jacobi_orth_t<E, G>(sm, nloc, E > 0 ? ld : len, ld, s_nrm, s_flag,
                                          zero_floor2(*d.fro2, nv, len, d.floor_eps), len, 1) > 0;
-    if (!any) return;
+    if (!any) return 0;
     for (int e = tid; e < nloc * ld; e += NT) {
         const int j = e / ld, l = e - j * ld;
         if (l >= len) continue;
         const int gj = j < c0 ? i0 + j : i1 + (j - c0);
         d.X[(size_t)gj * len + l] = sm[e];
     }
-    if (tid == 0 && d.conv) atomicOr(d.conv, 1);
+    return 1;
 }
+
+// One round of the single-problem blocked path: workgroup i takes the block
+// pair of tournament position i.
+template <int E, int G = 16>
+__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_kernel(JacobiDesc d, int rd) {
+    extern __shared__ double sm[];
+    __shared__ int s_flag, s_bad;
+    __shared__ double s_nrm[64];
+    if (panel_pair_round<E, G>(d, rd, (int)blockIdx.x, sm, &s_flag, &s_bad, s_nrm) > 0 && threadIdx.x == 0 &&
+        d.conv)
+        atomicOr(d.conv, 1);
+}
+
+// ---- persistent batched blocked path ----------------------------------------
+// One launch runs every sweep of every factorization of a batched step.
+// Workgroups form teams of P (the largest block-pair count of the launch);
+// a team takes factorizations from a device queue (the descriptor array,
+// ordered longest first on the host) and runs the tournament over blocks,
+// member m taking the pair of position m in every round, with a team barrier
+// between rounds, until a sweep rotates nothing (or the sweep budget runs
+// out, status bit 2).  The grid is at most one workgroup per compute unit,
+// so every team is resident; every wait is bounded all the same (status bit
+// 4 and the team stops when a barrier times out).
+
+__device__ __forceinline__ int ld_agent(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr long long PANEL_SPIN_LIMIT = 1LL << 22;
+
+// Team barrier number `phase` (1, 2, ... in every member): every thread
+// releases its global writes at agent scope, one thread per workgroup counts
+// the arrival and waits for phase * P arrivals, every thread acquires.
+// Returns false when the team has given up (a wait ran out).
+__device__ bool team_barrier(PanelTeamState* T, int P, int phase, int* s_ok) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __hip_atomic_fetch_add(&T->bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int target = phase * P;
+        long long spins = 0;
+        while (ld_agent(&T->bar) < target) {
+            if (ld_agent(&T->abort) || ++spins > PANEL_SPIN_LIMIT) {
+                st_agent(&T->abort, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_ok = ok && !ld_agent(&T->abort);
+    }
+    __syncthreads();
+    __threadfence();
+    return *s_ok != 0;
+}
+
+template <int E, int G = 16>
+__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_persistent_kernel(const JacobiDesc* arr,
+                                                                                     int count, int P,
+                                                                                     PanelQueueState* q,
+                                                                                     int max_sweeps) {
+    extern __shared__ double sm[];
+    __shared__ int s_flag, s_bad, s_ok, s_prob, s_rot;
+    __shared__ double s_nrm[64];
+    // team and member of this workgroup: with a team count divisible by 8 the
+    // members of a team share blockIdx mod 8, i.e. one XCD and its L2
+    const int b = (int)blockIdx.x, nteam = (int)gridDim.x / P;
+    int team, member;
+    if (nteam % 8 == 0) {
+        team = (b % 8) + 8 * ((b / 8) / P);
+        member = (b / 8) % P;
+    } else {
+        team = b / P;
+        member = b % P;
+    }
+    PanelTeamState* T = &q->team[team];
+    const int tid = threadIdx.x;
+    int phase = 0;
+    for (;;) {
+        // the leader takes the next factorization and clears the flags
+        int taken = -1;
+        if (member == 0 && tid == 0) {
+            const int p = __hip_atomic_fetch_add(&q->head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            taken = p < count ? p : -1;
+            st_agent(&T->prob, taken);
+            for (int k = 0; k < 3; ++k) st_agent(&T->rot[k], 0);
+        }
+        if (!team_barrier(T, P, ++phase, &s_ok)) {
+            if (taken >= 0 && arr[taken].status) atomicOr(arr[taken].status, 4);
+            return;
+        }
+        if (tid == 0) s_prob = ld_agent(&T->prob);
+        __syncthreads();
+        const int pi = s_prob;
+        if (pi < 0) return;
+        const JacobiDesc& d = arr[pi];
+        const int rounds = d.nblk - 1;
+        int sw = 0;
+        bool converged = false, alive = true;
+        for (; sw < max_sweeps && alive; ++sw) {
+            // slot (sw + 1) mod 3 was last read two sweeps ago: free for the next sweep
+            if (member == 0 && tid == 0) st_agent(&T->rot[(sw + 1) % 3], 0);
+            for (int rd = 0; rd < rounds && alive; ++rd) {
+                const int r = panel_pair_round<E, G>(d, rd, member, sm, &s_flag, &s_bad, s_nrm);
+                if (r > 0 && tid == 0)
+                    __hip_atomic_fetch_or(&T->rot[sw % 3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                alive = team_barrier(T, P, ++phase, &s_ok);
+            }
+            if (!alive) break;
+            if (tid == 0) s_rot = ld_agent(&T->rot[sw % 3]);
+            __syncthreads();
+            if (!s_rot) {
+                converged = true;
+                break;
+            }
+        }
+        if (member == 0 && tid == 0) {
+            if (!alive && d.status) atomicOr(d.status, 4);
+            else if (!converged && d.status) atomicOr(d.status, 2);
+            if (d.log_sweeps) *d.log_sweeps = sw;  // sweeps that rotated
+        }
+        if (!alive) return;
+        // every member has read this factorization's flags before the leader moves on
+        if (!team_barrier(T, P, ++phase, &s_ok)) return;
+    }
+}
+
 
 // One round of the global-memory path for matrices too large for LDS: wave w
 // of workgroup b takes pair 4 b + w of round rd of the round-robin tournament,
@@ -611,28 +737,6 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d0, const 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
-// Batched blocked path, between sweeps: a factorization that rotated nothing
-// in the sweep just finished is done; clear the rotation flags.
-__global__ void jacobi_sweep_end_kernel(const JacobiDesc* arr, int count) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        if (*arr[i].conv == 0) *arr[i].done = 1;
-        *arr[i].conv = 0;
-    }
-}
-
-// After the sweep budget: a factorization still rotating is reported (status bit 2).
-__global__ void jacobi_check_done_kernel(const JacobiDesc* arr, int count) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-        if (*arr[i].done == 0) atomicOr(arr[i].status, 2);
-}
-
-__global__ void jacobi_reset_kernel(const JacobiDesc* arr, int count) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        *arr[i].conv = 0;
-        *arr[i].done = 0;
-    }
-}
-
 // ||X||_F^2 for the blocked path's rank floor: per-vector sums in vector order.
 __global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d0, const JacobiDesc* arr) {
     const JacobiDesc d = arr ? arr[blockIdx.x] : d0;
@@ -662,11 +766,17 @@ __global__ __launch_bounds__(JT) void fro2_kernel(JacobiDesc d0, const JacobiDes
 // gfx950 device.
 constexpr int LDS_STATIC_RESERVE = 1024;
 static int g_lds_bytes = LDS_BYTES - LDS_STATIC_RESERVE;
+// Compute units of the device (gfx950: 256), the bound of a persistent grid.
+static int g_num_cu = 256;
 
 hipError_t jacobi_init(int device) {
     int lim = 0;
     hipError_t e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     if (e != hipSuccess) return e;
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    if (ncu > 0) g_num_cu = ncu;
     lim = lim < LDS_BYTES ? lim : LDS_BYTES;
     // the dynamic part may use what the kernels' static LDS leaves free
     size_t stat = 0;
@@ -679,7 +789,15 @@ hipError_t jacobi_init(int device) {
                              (const void*)jacobi_panel_kernel<0>, (const void*)jacobi_panel_kernel<1>,
                              (const void*)jacobi_panel_kernel<2>, (const void*)jacobi_panel_kernel<4>,
                              (const void*)jacobi_panel_kernel<8>, (const void*)jacobi_panel_kernel<16>,
-                             (const void*)jacobi_panel_kernel<16, 32>, (const void*)jacobi_panel_kernel<16, 64>};
+                             (const void*)jacobi_panel_kernel<16, 32>, (const void*)jacobi_panel_kernel<16, 64>,
+                             (const void*)jacobi_panel_persistent_kernel<0>,
+                             (const void*)jacobi_panel_persistent_kernel<1>,
+                             (const void*)jacobi_panel_persistent_kernel<2>,
+                             (const void*)jacobi_panel_persistent_kernel<4>,
+                             (const void*)jacobi_panel_persistent_kernel<8>,
+                             (const void*)jacobi_panel_persistent_kernel<16>,
+                             (const void*)jacobi_panel_persistent_kernel<16, 32>,
+                             (const void*)jacobi_panel_persistent_kernel<16, 64>};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -759,25 +877,48 @@ void jacobi_panel_params(int nvec_cap, int len_cap, int* bs_out, int* nblk_out) 
 }
 
 // One launch of the blocked path's round rd for the shape of len_cap.
-static void launch_panel_round(const PanelShape& ps, dim3 grid, size_t shm, hipStream_t s, const JacobiDesc& d0,
-                               const JacobiDesc* arr, int rd) {
+static void launch_panel_round(const PanelShape& ps, dim3 grid, size_t shm, hipStream_t s, const JacobiDesc& d,
+                               int rd) {
     const dim3 block(ps.threads);
     if (ps.G == 64) {
-        hipLaunchKernelGGL((jacobi_panel_kernel<16, 64>), grid, block, shm, s, d0, arr, rd);
+        hipLaunchKernelGGL((jacobi_panel_kernel<16, 64>), grid, block, shm, s, d, rd);
         return;
     }
     if (ps.G == 32) {
-        hipLaunchKernelGGL((jacobi_panel_kernel<16, 32>), grid, block, shm, s, d0, arr, rd);
+        hipLaunchKernelGGL((jacobi_panel_kernel<16, 32>), grid, block, shm, s, d, rd);
         return;
     }
     switch (ps.E) {
-        case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, grid, block, shm, s, d0, arr, rd); break;
-        case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, grid, block, shm, s, d0, arr, rd); break;
-        case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, grid, block, shm, s, d0, arr, rd); break;
-        case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, grid, block, shm, s, d0, arr, rd); break;
-        case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, grid, block, shm, s, d0, arr, rd); break;
-        default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, grid, block, shm, s, d0, arr, rd); break;
+        case 1: hipLaunchKernelGGL(jacobi_panel_kernel<1>, grid, block, shm, s, d, rd); break;
+        case 2: hipLaunchKernelGGL(jacobi_panel_kernel<2>, grid, block, shm, s, d, rd); break;
+        case 4: hipLaunchKernelGGL(jacobi_panel_kernel<4>, grid, block, shm, s, d, rd); break;
+        case 8: hipLaunchKernelGGL(jacobi_panel_kernel<8>, grid, block, shm, s, d, rd); break;
+        case 16: hipLaunchKernelGGL(jacobi_panel_kernel<16>, grid, block, shm, s, d, rd); break;
+        default: hipLaunchKernelGGL(jacobi_panel_kernel<0>, grid, block, shm, s, d, rd); break;
     }
+}
+
+// The persistent batched launch for the shape of len_cap.
+static void launch_panel_persistent(const PanelShape& ps, int grid, size_t shm, hipStream_t s,
+                                    const JacobiDesc* arr, int count, int P, PanelQueueState* q, int max_sweeps) {
+    const dim3 g(grid), block(ps.threads);
+#define SMPS_PANEL_PERSISTENT(...) \
+    hipLaunchKernelGGL((jacobi_panel_persistent_kernel<__VA_ARGS__>), g, block, shm, s, arr, count, P, q, max_sweeps)
+    if (ps.G == 64) {
+        SMPS_PANEL_PERSISTENT(16, 64);
+    } else if (ps.G == 32) {
+        SMPS_PANEL_PERSISTENT(16, 32);
+    } else {
+        switch (ps.E) {
+            case 1: SMPS_PANEL_PERSISTENT(1); break;
+            case 2: SMPS_PANEL_PERSISTENT(2); break;
+            case 4: SMPS_PANEL_PERSISTENT(4); break;
+            case 8: SMPS_PANEL_PERSISTENT(8); break;
+            case 16: SMPS_PANEL_PERSISTENT(16); break;
+            default: SMPS_PANEL_PERSISTENT(0); break;
+        }
+    }
+#undef SMPS_PANEL_PERSISTENT
 }
 
 size_t jacobi_work_doubles(int, int) { return 0; }
@@ -853,7 +994,7 @@ static void enqueue_round_sweep(const JacobiDesc& dd, int rounds, int ew, dim3 g
 // round of the tournament over blocks.
 static void enqueue_panel_sweep(const JacobiDesc& dd, const PanelShape& ps, size_t shm, int* flags, hipStream_t s) {
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, s, flags);
-    for (int rd = 0; rd < dd.nblk - 1; ++rd) launch_panel_round(ps, dim3(dd.nblk / 2), shm, s, dd, nullptr, rd);
+    for (int rd = 0; rd < dd.nblk - 1; ++rd) launch_panel_round(ps, dim3(dd.nblk / 2), shm, s, dd, rd);
 }
 
 // ew > 0: a sweep of the round kernel with ew elements per lane; ew == 0: a
@@ -989,22 +1130,28 @@ hipError_t launch_jacobi_lds_batched(const JacobiDesc* arr, int count, int E, si
     return hipGetLastError();
 }
 
-// Every descriptor carries bs / nblk / conv / done / fro2.  A fixed number of
-// sweeps is enqueued (no host read-back, so the sequence can be captured in a
-// graph); factorizations that converge earlier skip the remaining rounds.
-hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_nblk,
-                                       int max_rows, int len_cap, size_t shm, int sweeps, hipStream_t s) {
+int jacobi_panel_teams(int count, int max_pairs) {
+    int teams = std::max(1, std::min(count, g_num_cu / std::max(1, max_pairs)));
+    teams = std::min(teams, PANEL_MAX_TEAMS);
+    if (teams >= 8) teams -= teams % 8;
+    return teams;
+}
+
+// Every descriptor carries bs / nblk / fro2; q is the launch's queue state
+// (PANEL_QUEUE_BYTES).  Five kernels whatever the sweep count: queue reset,
+// norms, the persistent sweeps, selection, write-back.
+hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_rows, int len_cap,
+                                       size_t shm, PanelQueueState* q, hipStream_t s) {
     if (count <= 0) return hipSuccess;
+    // a team must fit on the device at one workgroup per compute unit
+    if (max_pairs < 1 || max_pairs > g_num_cu) return hipErrorInvalidValue;
     JacobiDesc none{};
-    hipLaunchKernelGGL(jacobi_reset_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    hipError_t e = launch_zero_ints((int*)q, (int)(PANEL_QUEUE_BYTES / sizeof(int)), s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fro2_kernel, dim3(count), dim3(JT), 0, s, none, arr);
     const PanelShape ps = panel_shape(len_cap);
-    const dim3 grid(max_pairs, count);
-    for (int sw = 0; sw < sweeps; ++sw) {
-        for (int rd = 0; rd < max_nblk - 1; ++rd) launch_panel_round(ps, grid, shm, s, none, arr, rd);
-        hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(1), dim3(256), 0, s, arr, count);
-    }
-    hipLaunchKernelGGL(jacobi_check_done_kernel, dim3(1), dim3(256), 0, s, arr, count);
+    const int teams = jacobi_panel_teams(count, max_pairs);
+    launch_panel_persistent(ps, teams * max_pairs, shm, s, arr, count, max_pairs, q, ROUND_MAX_SWEEPS);
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(count), dim3(JT), 0, s, none, arr);
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, max_rows, count), dim3(256), 0, s, none,
                        arr);

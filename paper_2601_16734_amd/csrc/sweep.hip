@@ -940,6 +940,7 @@ struct Enq {
 
 static const char* status_message(int status) {
     if (status & 1) return "non-finite values in a two-site tensor or the result";
+    if (status & 4) return "a persistent blocked factorization gave up waiting for its team (barrier time-out)";
     return "a blocked factorization did not converge within its sweep budget";
 }
 
@@ -1090,14 +1091,11 @@ int run_autotune(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_s
 // Batched execution
 // ---------------------------------------------------------------------------
 
-constexpr int PANEL_SWEEPS_BATCHED = 40;
-
-// Kernel nodes one batched graph may hold.  The blocked factorization enqueues
-// its whole sweep budget (rounds x sweeps) per step, so a chain with two-site
-// tensors far beyond the LDS multiplies the graph: the 512-chain QTT batch
-// needs about 8e4 nodes; a single L = 100, chi = 256 chain about 2.2e5 per
-// sweep, and such a capture ended the process on the host.  Larger batches
-// are refused (such chains belong on the single-problem path).
+// Kernel nodes one batched graph may hold.  Every operation of a step is a
+// bounded number of kernels (the blocked factorization runs all its sweeps in
+// one persistent launch), so a graph grows with the steps of its longest
+// chain: a batch holding an L = 100 chain with 4 sweeps needs about 2e4.  The
+// bound keeps host memory and instantiation time of one capture in check.
 constexpr long long MAX_GRAPH_KERNELS = 100000;
 
 struct IntSetDesc {
@@ -1176,6 +1174,7 @@ struct Launch {
     bool panel = false;
     bool acc = false;  // LDS Jacobi launch: rotations accumulated
     int max_pairs = 0, max_nblk = 0, max_rows = 0;
+    size_t queue_off = 0;  // persistent blocked launch: its queue state in the arena
 };
 
 struct BatchCache {
@@ -1201,6 +1200,8 @@ static std::vector<int> launch_signature(const Op& op) {
 }
 
 static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& da, std::vector<Launch>& out) {
+    // the persistent blocked launches run one after another: they share one queue state
+    size_t queue_off = SIZE_MAX;
     // group equal tags (phase, step, slot) across problems, in sequence order;
     // within a tag, problems whose ops differ in kind or template arguments (a
     // step can be shaped differently in chains of different lengths) get
@@ -1279,7 +1280,11 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                     }
                 }
                 // the blocked launch's row layout follows its longest rows: every
-                // factorization in it takes that shape's block size
+                // factorization in it takes that shape's block size.  The array is
+                // the persistent launch's queue: largest (nvec^2 len) first
+                std::stable_sort(blocked.begin(), blocked.end(), [](const Op* a, const Op* b) {
+                    return (double)a->cap0 * a->cap0 * a->cap1 > (double)b->cap0 * b->cap0 * b->cap1;
+                });
                 std::vector<JacobiDesc> panel;
                 for (const Op* o : blocked) {
                     JacobiDesc d = o->jd;
@@ -1303,6 +1308,11 @@ static void build_launches(const std::vector<std::vector<Op>>& ops, DescArena& d
                 if (!panel.empty()) {
                     pl.count = (int)panel.size();
                     pl.off = da.add(panel.data(), sizeof(JacobiDesc) * panel.size());
+                    if (queue_off == SIZE_MAX) {
+                        const std::vector<char> zero(PANEL_QUEUE_BYTES, 0);
+                        queue_off = da.add(zero.data(), zero.size());
+                    }
+                    pl.queue_off = queue_off;
                     out.push_back(pl);
                 }
                 break;
@@ -1356,7 +1366,7 @@ static long long graph_kernels(const std::vector<Launch>& ls) {
     long long n = 1;  // the gather
     for (const Launch& l : ls) {
         if (l.kind == OP_JAC && l.panel)
-            n += 5 + (long long)PANEL_SWEEPS_BATCHED * l.max_nblk;
+            n += 5;  // queue reset, norms, persistent sweeps, selection, write-back
         else
             n += 2;
     }
@@ -1379,8 +1389,8 @@ static hipError_t enqueue_launches(const std::vector<Launch>& ls, char* dev, hip
                 break;
             case OP_JAC:
                 if (l.panel)
-                    e = launch_jacobi_panel_batched((const JacobiDesc*)arr, l.count, l.max_pairs, l.max_nblk,
-                                                    l.max_rows, l.cap1, l.shm, PANEL_SWEEPS_BATCHED, s);
+                    e = launch_jacobi_panel_batched((const JacobiDesc*)arr, l.count, l.max_pairs, l.max_rows, l.cap1,
+                                                    l.shm, (PanelQueueState*)(dev + l.queue_off), s);
                 else
                     e = launch_jacobi_lds_batched((const JacobiDesc*)arr, l.count, l.E, l.shm, s, l.acc);
                 break;

@@ -142,15 +142,52 @@ def test_single_blocked_path_vs_oracle(ctx, qtt_sample):
 
 
 def test_batched_refuses_a_graph_beyond_its_kernel_limit(ctx):
-    # the L=100 chi=256 chain's 512 x 512 two-site tensors take the blocked
-    # factorization, whose full sweep budget per step would put about 2.2e5
-    # kernels in one graph: refused before anything is captured
-    w = synth.workload_xxz()
-    v, U = ctx.mps_create(w.mps), ctx.mpo_create(w.mpo)
+    # every step adds a bounded number of kernels (the blocked factorization
+    # runs all its sweeps in one persistent launch), so only a very long chain
+    # reaches the graph limit: L = 1000 with 4 sweeps, refused before capture
+    L = 1000
+    phys, bonds = [2] * L, synth.bond_caps(L, 2, 8)
+    v = ctx.mps_zeros(phys, bonds)
+    U = ctx.mpo_zeros(phys, phys, [1] + [2] * (L - 1) + [1])
+    st = B.strategy(8, 1e-10, sweeps=4)
     with pytest.raises(B.SmpsError) as e:
-        ctx.mpo_apply_batched([U], [v], B.strategy(256, 1e-10, sweeps=1))
+        ctx.plan_apply_batched([U], [v], st)
+    assert e.value.code == B.EUNSUPPORTED and e.value.info["graph_kernels"] > 100000
+    with pytest.raises(B.SmpsError) as e:
+        ctx.mpo_apply_batched([U], [v], st)
     assert e.value.code == B.EUNSUPPORTED
     assert "limit" in str(e.value)
+    v.destroy()
+    U.destroy()
+
+
+def test_l100_chi256_chain_in_a_batch_matches_the_oracle_run(ctx):
+    # the chain whose batched capture once held 2.2e5 kernels: its 512 x 512
+    # two-site tensors take the persistent blocked factorization; the batch
+    # also holds a short chain of the QTT batch.  Against the oracle's whole
+    # run (tests/golden, 4 sweeps, FP64): bonds, norm, error bound, probes.
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "xxz_L100_chi256_s4.json")))
+    w = synth.workload_xxz(0)
+    small = synth.workload_batch(0)[0]
+    vs, Us = upload(ctx, [w, small])
+    plan = ctx.plan_apply_batched(Us, vs, B.strategy(256, 1e-10, sweeps=4))
+    assert plan["graph_kernels"] < 100000
+    outs, errs = ctx.mpo_apply_batched(Us, vs, B.strategy(256, 1e-10, sweeps=4))
+    got = outs[0].read()
+    assert [1] + [t.shape[2] for t in got] == g["ranks"]
+    assert rel_norm_err(ctx.norm(outs[0]), g["norm"]) <= 1e-10
+    slack = sum(1e-9 * np.sqrt(n2 + d) for n2, d in zip(g["step_norms2"], g["step_deltas"]))
+    assert abs(errs[0] - g["error_bound"]) <= 1e-6 * g["error_bound"] + slack
+    probes = [synth.random_mps(synth.rng_for(90, i), 100, 2, 8) for i in range(3)]
+    for p, ref in zip(probes, g["probe_overlaps"]):
+        assert abs(om.scprod(p, got) - ref) <= 1e-6 * abs(ref)
+    # the short chain (max bond 256 here, above its own chi): its oracle run
+    ref = om.apply_simplify([np.asarray(x, np.float64) for x in small.mpo],
+                            [np.asarray(x, np.float64) for x in small.mps], 256, 1e-10, sweeps=4)
+    assert rel_norm_err(ctx.norm(outs[1]), ref.norm) <= 1e-10
+    assert [1] + [t.shape[2] for t in outs[1].read()] == ref.ranks
 
 
 def test_batched_blocked_launch_with_long_and_short_rows(ctx):

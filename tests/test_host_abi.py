@@ -4,8 +4,8 @@ workspace limits and planning, in a planning context (no device).
 Two builds run the same calls: the library as built (through the binding),
 and the library built with the host code under the address and
 undefined-behaviour sanitizers, driven by tests/host/abi_check.cpp -- which
-also records the batched launch sequence of one L=100, chi=256 chain (the
-capture that exceeds the graph kernel limit) and of the 512-chain QTT batch,
+also records the batched launch sequence of one L=100, chi=256 chain, of an
+L=1000 chain (beyond the graph kernel limit) and of the 512-chain QTT batch,
 so that the recording, the launch merging and the kernel count run under
 the sanitizers."""
 
@@ -169,14 +169,20 @@ def test_plan_follows_the_sweep(pctx, L, chi, D, sweeps):
 
 
 def test_batched_plan_counts_the_graph_and_refuses_beyond_the_limit(pctx):
+    # L = 100, chi = 256: the 512 x 512 two-site tensors take the persistent
+    # blocked factorization, a bounded number of kernels per step
     st = B.strategy(256, 1e-10, sweeps=4)
     U, v = make(pctx, 100, 2, 256, 5)
+    info = pctx.plan_apply_batched([U], [v], st)
+    assert info["steps"] == 2 * 4 * 99
+    assert info["graph_kernels"] <= 40 * info["steps"]
+    # only a very long chain exceeds the capture limit
+    U, v = make(pctx, 1000, 2, 8, 2)
     code, msg = code_of(pctx.plan_apply_batched, [U], [v], st)
     assert code == B.EUNSUPPORTED and "kernels" in msg
     with pytest.raises(B.SmpsError) as e:
         pctx.plan_apply_batched([U], [v], st)
     assert e.value.info["graph_kernels"] > MAX_GRAPH_KERNELS
-    assert e.value.info["steps"] == 2 * 4 * 99
 
 
 def batch_groups(ctx):
@@ -239,6 +245,7 @@ def test_sanitized_build_drives_validation_planning_and_batched_recording(abi_ex
     s.ctx()
     u_small, v_small = s.chain(0, *chain_shapes(20, 2, 64, 8))
     u_big, v_big = s.chain(0, *chain_shapes(100, 2, 256, 5))
+    u_long, v_long = s.chain(0, *chain_shapes(1000, 2, 8, 2))
     _, v_other = s.chain(1, *chain_shapes(20, 2, 64, 8))
     groups = {}
     for w in synth.workload_batch(0):
@@ -255,7 +262,8 @@ def test_sanitized_build_drives_validation_planning_and_batched_recording(abi_ex
 
     add(f"plan 0 {u_small} {v_small} {strategy_line(64)}", ("rc", 0))
     add(f"plan 0 {u_big} {v_big} {strategy_line(256)}", ("rc", 0))
-    add(f"planb 0 1 {u_big} {v_big} {strategy_line(256)}", ("big", B.EUNSUPPORTED))
+    add(f"planb 0 1 {u_big} {v_big} {strategy_line(256)}", ("group", 0))
+    add(f"planb 0 1 {u_long} {v_long} {strategy_line(8)}", ("big", B.EUNSUPPORTED))
     for chi, pairs in sorted(groups.items()):
         add(f"planb 0 {len(pairs)} {' '.join(f'{a} {b}' for a, b in pairs)} {strategy_line(chi)}", ("group", 0))
     add(f"apply 0 {u_small} {v_small} {strategy_line(0)}", ("rc", B.EINVAL))
