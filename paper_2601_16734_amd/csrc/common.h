@@ -129,11 +129,7 @@ hipError_t launch_gemm_tile(const GemmDesc& g, const GemmDesc* arr, int M_cap, i
 int gemm_tile_for(const GemmDesc& g, int M_cap, int N_cap, int prec);
 hipError_t launch_left_mpo(const LeftMpoDesc& d, int a_cap, hipStream_t s);
 hipError_t launch_right_mpo(const RightMpoDesc& d, int c_cap, hipStream_t s);
-// Exact factorization.  Chooses the LDS-resident kernel when nvec_cap*len_cap
-// fits, otherwise the blocked multi-workgroup path (which needs `work`:
-// at least jacobi_work_doubles(nvec_cap, len_cap) doubles).
-hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags,
-                         hipStream_t s);
+
 size_t jacobi_work_doubles(int nvec_cap, int len_cap);
 // Gram / tridiagonal / divide-and-conquer split (gtd.hip): rows of at most
 // 128 elements (and at most 1024 rows); `work` holds gtd_work_doubles doubles.
@@ -170,6 +166,13 @@ constexpr size_t PANEL_QUEUE_BYTES = sizeof(PanelQueueState);
 int jacobi_panel_teams(int count, int max_pairs);
 hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_rows, int len_cap,
                                        size_t shm, PanelQueueState* q, hipStream_t s);
+// Exact factorization.  Chooses the LDS-resident kernel when nvec_cap*len_cap
+// fits (or the Gram split when `work` is given and the size allows),
+// otherwise the blocked multi-workgroup path: one persistent team when
+// `queue` (PANEL_QUEUE_BYTES of device memory) is given, else one launch per
+// round with the sweeps driven from the host (`flags`: one device int).
+hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s,
+                         PanelQueueState* queue = nullptr);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
                                hipStream_t s, int prec);
 hipError_t launch_left_mpo_batched(const LeftMpoDesc* arr, int count, const LeftMpoDesc& types, int a_cap,

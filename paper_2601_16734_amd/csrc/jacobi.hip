@@ -543,16 +543,19 @@ __device__ __forceinline__ void st_agent(int* p, int v) {
 
 constexpr long long PANEL_SPIN_LIMIT = 1LL << 22;
 
-// Team barrier number `phase` (1, 2, ... in every member): every thread
-// releases its global writes at agent scope, one thread per workgroup counts
-// the arrival and waits for phase * P arrivals, every thread acquires.
-// Returns false when the team has given up (a wait ran out).
+// Team barrier number `phase` (1, 2, ... in every member).  Every wave first
+// waits for its own memory operations (so this workgroup's stores have
+// reached its L2 and no load is left in flight); one thread then counts the
+// arrival with a release at agent scope (the L2 write-back that makes the
+// stores visible to the other XCDs), waits for phase * P arrivals and
+// acquires at agent scope (invalidating the caches the whole workgroup
+// reads through).  Returns false when the team has given up (a wait ran out).
 __device__ bool team_barrier(PanelTeamState* T, int P, int phase, int* s_ok) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __hip_atomic_fetch_add(&T->bar, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&T->bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const int target = phase * P;
         long long spins = 0;
         while (ld_agent(&T->bar) < target) {
@@ -563,15 +566,16 @@ __device__ bool team_barrier(PanelTeamState* T, int P, int phase, int* s_ok) {
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_ok = ok && !ld_agent(&T->abort);
     }
     __syncthreads();
-    __threadfence();
     return *s_ok != 0;
 }
 
 template <int E, int G = 16>
-__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_persistent_kernel(const JacobiDesc* arr,
+__global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_persistent_kernel(JacobiDesc d0,
+                                                                                     const JacobiDesc* arr,
                                                                                      int count, int P,
                                                                                      PanelQueueState* q,
                                                                                      int max_sweeps) {
@@ -602,14 +606,15 @@ __global__ __launch_bounds__(panel_threads(E, G)) void jacobi_panel_persistent_k
             for (int k = 0; k < 3; ++k) st_agent(&T->rot[k], 0);
         }
         if (!team_barrier(T, P, ++phase, &s_ok)) {
-            if (taken >= 0 && arr[taken].status) atomicOr(arr[taken].status, 4);
+            int* st = taken < 0 ? nullptr : arr ? arr[taken].status : d0.status;
+            if (st) atomicOr(st, 4);
             return;
         }
         if (tid == 0) s_prob = ld_agent(&T->prob);
         __syncthreads();
         const int pi = s_prob;
         if (pi < 0) return;
-        const JacobiDesc& d = arr[pi];
+        const JacobiDesc d = arr ? arr[pi] : d0;
         const int rounds = d.nblk - 1;
         int sw = 0;
         bool converged = false, alive = true;
@@ -710,7 +715,6 @@ __global__ __launch_bounds__(JT) void jacobi_select_kernel(JacobiDesc d0, const 
     __shared__ double s_delta;
     const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
     jacobi_select(d.X, nv, len, len, sig_raw, sig_sorted, perm_s, d, &s_delta);
-    if (threadIdx.x == 0 && d.log_sweeps) *d.log_sweeps = 0;  // the single path's host loop sets its count after
     for (int j = threadIdx.x; j < nv; j += JT) d.perm[j] = perm_s[j];
 }
 
@@ -898,12 +902,14 @@ static void launch_panel_round(const PanelShape& ps, dim3 grid, size_t shm, hipS
     }
 }
 
-// The persistent batched launch for the shape of len_cap.
-static void launch_panel_persistent(const PanelShape& ps, int grid, size_t shm, hipStream_t s,
+// The persistent launch for the shape of len_cap: the factorizations of arr
+// (count of them), or d0 alone when arr is NULL.
+static void launch_panel_persistent(const PanelShape& ps, int grid, size_t shm, hipStream_t s, const JacobiDesc& d0,
                                     const JacobiDesc* arr, int count, int P, PanelQueueState* q, int max_sweeps) {
     const dim3 g(grid), block(ps.threads);
-#define SMPS_PANEL_PERSISTENT(...) \
-    hipLaunchKernelGGL((jacobi_panel_persistent_kernel<__VA_ARGS__>), g, block, shm, s, arr, count, P, q, max_sweeps)
+#define SMPS_PANEL_PERSISTENT(...)                                                                                  \
+    hipLaunchKernelGGL((jacobi_panel_persistent_kernel<__VA_ARGS__>), g, block, shm, s, d0, arr, count, P, q, \
+                       max_sweeps)
     if (ps.G == 64) {
         SMPS_PANEL_PERSISTENT(16, 64);
     } else if (ps.G == 32) {
@@ -1059,7 +1065,8 @@ static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, di
     return hipSuccess;
 }
 
-hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
+hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s,
+                         PanelQueueState* queue) {
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
     // exact splits of short rows: the Gram / tridiagonal / divide-and-conquer
     // path when the caller provides its workspace
@@ -1081,6 +1088,21 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
     hipGraphExec_t exec = nullptr;
     const PanelShape ps = panel_shape(len_cap);
+    if (queue && len_cap <= 1024 && ps.bs >= 1) {
+        // blocked path as one persistent team: every sweep on the device, no
+        // host round trip per sweep
+        jacobi_panel_params(nvec_cap, len_cap, &dd.bs, &dd.nblk);
+        const int P = dd.nblk / 2;
+        if (P > g_num_cu) return hipErrorInvalidValue;
+        hipError_t e = launch_zero_ints((int*)queue, (int)(PANEL_QUEUE_BYTES / sizeof(int)), s);
+        if (e != hipSuccess) return e;
+        launch_panel_persistent(ps, P, jacobi_panel_bytes(len_cap, dd.bs), s, dd, nullptr, 1, P, queue,
+                                ROUND_MAX_SWEEPS);
+        hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
+        const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
+        hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
+        return hipGetLastError();
+    }
     if (len_cap <= 1024 && ps.bs >= 1) {
         // blocked path: a tournament over blocks of rows, each block pair
         // orthogonalised in LDS (one inner sweep), one launch per round
@@ -1151,7 +1173,7 @@ hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max
     hipLaunchKernelGGL(fro2_kernel, dim3(count), dim3(JT), 0, s, none, arr);
     const PanelShape ps = panel_shape(len_cap);
     const int teams = jacobi_panel_teams(count, max_pairs);
-    launch_panel_persistent(ps, teams * max_pairs, shm, s, arr, count, max_pairs, q, ROUND_MAX_SWEEPS);
+    launch_panel_persistent(ps, teams * max_pairs, shm, s, none, arr, count, max_pairs, q, ROUND_MAX_SWEEPS);
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(count), dim3(JT), 0, s, none, arr);
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, max_rows, count), dim3(256), 0, s, none,
                        arr);

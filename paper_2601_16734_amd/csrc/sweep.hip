@@ -350,7 +350,11 @@ struct Enq {
             case OP_RIGHT: return launch_right_mpo(op.r, op.cap0, s);
             case OP_JAC: {
                 const int tok = ctx ? prof_begin(ctx, s) : -1;
-                hipError_t e = launch_jacobi(op.jd, op.cap0, op.cap1, gtd_on(op.cap0, op.cap1) ? at<double>(p.o_gtd) : nullptr,
+                // the blocked path stays host-driven here: measured at 512 and 1024
+                // element rows, one launch per round beats a persistent team whose
+                // members sit on different XCDs (team barriers cost more than launches)
+                hipError_t e = launch_jacobi(op.jd, op.cap0, op.cap1,
+                                             gtd_on(op.cap0, op.cap1) ? at<double>(p.o_gtd) : nullptr,
                                              at<int>(p.o_flag), s);
                 // category 2 also counts the splits of the largest (bulk) two-site tensor
                 if (ctx) prof_end(ctx, s, tok, 0, op.cap0 == p.max_nvec && op.cap1 == p.max_nvec ? 2 : -1);
