@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--batched", action="store_true",
                     help="only measure the 512-chain QTT batch (batched by chi, graph-captured, FP64 and mixed; "
                          "against a per-chain loop) and print its JSON line")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="--batched: skip the per-chain loop comparison (for profiling the batched call)")
     ap.add_argument("--replicas", type=int, default=0, metavar="N",
                     help="only measure N independent copies of the headline workload (n=20 chi=64 D=8, 4 sweeps) "
                          "in one batched, graph-captured call and print its JSON line")
@@ -557,12 +559,13 @@ def large_leg(args):
 def batched_leg(args):
     """The 512-chain QTT batch (n uniform in [8, 30], chi uniform in
     {4, 8, ..., 128}, FP32 N(0, 1/chi) entries, bond-3 Laplacian or bond-2
-    shift): every chain compressed at its own chi (tol 1e-10, 4 sweeps); the
-    chains are grouped by chi and each group runs as one batched, graph-captured
-    call.  The capture call is untimed; the timed call replays the graphs.
-    Compared with a loop of single-chain calls on the first 32 chains.  The
-    oracle checks a sample (the first 16 chains) and is timed on the first
-    chains in order, within the CPU budget, on one thread."""
+    shift): every chain compressed at its own chi (tol 1e-10, 4 sweeps) in
+    one batched call -- one graph for all 512 chains, per-chain bond caps,
+    the blocked factorizations run by persistent teams from a longest-first
+    queue.  The capture call is untimed; the timed calls replay the graph.
+    Compared with a loop of single-chain calls over all 512 chains (FP64).
+    The oracle checks a sample (the first 16 chains) and is timed on the
+    first chains in order, within the CPU budget, on one thread."""
     import numpy as np
     import torch
 
@@ -575,70 +578,48 @@ def batched_leg(args):
     sweeps = 4
     vs = [ctx.mps_create(w.mps, dtype=np.float32) for w in ws]
     Us = [ctx.mpo_create(w.mpo) for w in ws]
-    groups = {}
-    for i, w in enumerate(ws):
-        groups.setdefault(w.max_bond, []).append(i)
+    caps = [w.max_bond for w in ws]
     steps_of = [sweeps * 2 * (w.meta["n"] - 1) for w in ws]
     su = sum(steps_of)
     precs = [p for p in args.precisions.split(",") if p != "bf16"]
     results, outs = {}, {}
+    plan = ctx.plan_apply_batched(Us, vs, B.strategy(max(caps), 1e-10, sweeps=sweeps), max_bonds=caps)
     for prec in precs:
-        per_group, tot = {}, 0.0
-        outs[prec] = [None] * len(ws)
-        for cap, idx in sorted(groups.items()):
-            st = B.strategy(cap, 1e-10, sweeps=sweeps, precision=prec)
-            first, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)  # capture
-            for o in first:
-                o.destroy()
-            torch.cuda.synchronize()
-            times = []
-            for _ in range(max(1, args.steps)):
-                t = time.perf_counter()
-                got, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t)
-                for j, i in enumerate(idx):
-                    if outs[prec][i] is not None:
-                        outs[prec][i].destroy()
-                    outs[prec][i] = got[j]
-            sec = float(np.median(times))
-            tot += sec
-            g_su = sum(steps_of[i] for i in idx)
-            per_group[str(cap)] = {"chains": len(idx), "site_updates": g_su, "ms": 1e3 * sec,
-                                   "site_updates_per_s": g_su / sec}
-        results[prec] = {"ms_per_step": 1e3 * tot, "site_updates_per_s": su / tot, "per_chi": per_group}
-        print(f"batched leg: {prec} {su / tot:.0f} site-updates/s", file=sys.stderr, flush=True)
-    # per-chain loop (single-problem calls) on the first 32 chains, FP64
-    loop_idx = list(range(32))
-    for i in loop_idx[:2]:  # warm-up
-        o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(ws[i].max_bond, 1e-10, sweeps=sweeps))
-        o.destroy()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in loop_idx:
-        o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(ws[i].max_bond, 1e-10, sweeps=sweeps))
-        o.destroy()
-    torch.cuda.synchronize()
-    loop_sec = time.perf_counter() - t
-    loop_rate = sum(steps_of[i] for i in loop_idx) / loop_sec
-    # the same 32 chains batched (FP64) for a like-for-like ratio
-    sub = {}
-    for i in loop_idx:
-        sub.setdefault(ws[i].max_bond, []).append(i)
-    sub_sec = 0.0
-    for cap, idx in sorted(sub.items()):
-        st = B.strategy(cap, 1e-10, sweeps=sweeps)
-        first, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
+        st = B.strategy(max(caps), 1e-10, sweeps=sweeps, precision=prec)
+        t = time.perf_counter()
+        first, _ = ctx.mpo_apply_batched(Us, vs, st, max_bonds=caps)  # capture + first replay
+        torch.cuda.synchronize()
+        capture_sec = time.perf_counter() - t
         for o in first:
             o.destroy()
+        times = []
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            got, _ = ctx.mpo_apply_batched(Us, vs, st, max_bonds=caps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            for i in range(len(ws)):
+                if outs.setdefault(prec, [None] * len(ws))[i] is not None:
+                    outs[prec][i].destroy()
+                outs[prec][i] = got[i]
+        sec = float(np.median(times))
+        results[prec] = {"ms_per_step": 1e3 * sec, "site_updates_per_s": su / sec,
+                         "first_call_with_capture_ms": 1e3 * capture_sec}
+        print(f"batched leg: {prec} {su / sec:.0f} site-updates/s", file=sys.stderr, flush=True)
+    # per-chain loop (single-problem calls) over all 512 chains, FP64
+    loop_sec = loop_rate = float("nan")
+    for i in range(0 if args.no_loop else 4):  # warm-up
+        o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(caps[i], 1e-10, sweeps=sweeps))
+        o.destroy()
+    if not args.no_loop:
         torch.cuda.synchronize()
         t = time.perf_counter()
-        got, _ = ctx.mpo_apply_batched([Us[i] for i in idx], [vs[i] for i in idx], st)
-        torch.cuda.synchronize()
-        sub_sec += time.perf_counter() - t
-        for o in got:
+        for i in range(len(ws)):
+            o, _ = ctx.mpo_apply(Us[i], vs[i], B.strategy(caps[i], 1e-10, sweeps=sweeps))
             o.destroy()
-    sub_rate = sum(steps_of[i] for i in loop_idx) / sub_sec
+        torch.cuda.synchronize()
+        loop_sec = time.perf_counter() - t
+        loop_rate = su / loop_sec
     cpu = None
     if not args.no_cpu:
         from oracle import mps as om
@@ -692,14 +673,15 @@ def batched_leg(args):
             "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16x3": "bf16x3+f64"}[best_p], "data": "synthetic",
             "config": {"workload": "512 QTT chains, n uniform in [8,30], d=2, chi uniform in {4,...,128}, FP32 "
                                    "entries, bond-3 Laplacian or bond-2 shift MPO, max bond chi, tol 1e-10, 4 sweeps; "
-                                   "batched by chi, graph-captured", "site_updates_per_step": su,
-                       "precision": best_p},
+                                   "one batched call (per-chain caps), one graph", "site_updates_per_step": su,
+                       "precision": best_p, "graph_kernels": plan["graph_kernels"],
+                       "batched_launches": plan["launches"]},
             "fp64_site_updates_per_s": fp64["site_updates_per_s"] if fp64 else None,
             "speedup_vs_fp64": best["site_updates_per_s"] / fp64["site_updates_per_s"] if fp64 else None,
             "per_precision": results,
-            "per_chain_loop_first32_fp64": {"site_updates_per_s": loop_rate,
-                                            "batched_same_32_fp64_site_updates_per_s": sub_rate,
-                                            "batched_over_loop": sub_rate / loop_rate},
+            "per_chain_loop_all512_fp64": None if args.no_loop else
+            {"site_updates_per_s": loop_rate, "seconds": loop_sec,
+             "batched_fp64_over_loop": (fp64["site_updates_per_s"] / loop_rate) if fp64 else None},
             "cpu_baseline": cpu}
     print(json.dumps(line))
     ctx.close()

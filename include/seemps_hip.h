@@ -313,6 +313,13 @@ int smps_dmrg(smps_ctx *ctx, const smps_mpo *H, const smps_mps *guess, const smp
    out[i] as for smps_mpo_apply; trunc_err (nullable) has n entries. */
 int smps_mpo_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
                            const smps_strategy *strategy, smps_mps **out, double *trunc_err);
+/* The same with a bond cap per problem: max_bonds[i] (>= 1) replaces
+   strategy->max_bond for problem i, so that chains compressed at different
+   caps share one batch (one graph).  max_bonds NULL: the strategy's cap for
+   every problem (= smps_mpo_apply_batched). */
+int smps_mpo_apply_batched_caps(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
+                                const int *max_bonds, const smps_strategy *strategy, smps_mps **out,
+                                double *trunc_err);
 
 /* ---- planning (host only) ------------------------------------------------------
  * What smps_mpo_apply (one problem) or smps_mpo_apply_batched (n problems)
@@ -333,8 +340,9 @@ typedef struct {
 } smps_plan_info;
 int smps_plan_apply(smps_ctx *ctx, const smps_mpo *U, const smps_mps *v, const smps_strategy *strategy,
                     smps_plan_info *info);
+/* max_bonds: as for smps_mpo_apply_batched_caps (NULL: the strategy's cap). */
 int smps_plan_apply_batched(smps_ctx *ctx, int n, const smps_mpo *const *U, const smps_mps *const *v,
-                            const smps_strategy *strategy, smps_plan_info *info);
+                            const int *max_bonds, const smps_strategy *strategy, smps_plan_info *info);
 
 /* ---- scalar product and norm (Sec. 2.4.4) -------------------------------------
  * scprod: <a, b> by the transfer-matrix sweep, O(L chi^3 d), FP64.

@@ -34,7 +34,8 @@ EXPORTS = [
     "smps_mps_device_ptr", "smps_mpo_create", "smps_mpo_destroy", "smps_mpo_apply", "smps_simplify",
     "smps_last_info", "smps_last_log", "smps_last_factor_log", "smps_combine", "smps_mpo_transpose",
     "smps_mpo_apply_right", "smps_mpo_list_apply", "smps_mpo_simplify", "smps_mpo_shape", "smps_mpo_read",
-    "smps_mpo_apply_batched", "smps_plan_apply", "smps_plan_apply_batched", "smps_scprod", "smps_norm",
+    "smps_mpo_apply_batched", "smps_mpo_apply_batched_caps", "smps_plan_apply", "smps_plan_apply_batched",
+    "smps_scprod", "smps_norm",
     "smps_scprod_noalloc",
     "smps_rank_mlp_init", "smps_rank_mlp_train", "smps_rank_mlp_predict", "smps_rank_mlp_get",
     "smps_rank_mlp_set", "smps_rank_mlp_grad", "smps_rank_training_pairs",
@@ -90,8 +91,10 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "smps_ctx_create_planning": (c_int, [POINTER(vp)]),
         "smps_ctx_set_workspace_limit": (c_int, [vp, c_size_t]),
         "smps_plan_apply": (c_int, [vp, vp, vp, POINTER(Strategy), POINTER(PlanInfo)]),
-        "smps_plan_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), POINTER(Strategy),
+        "smps_plan_apply_batched": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), ip, POINTER(Strategy),
                                             POINTER(PlanInfo)]),
+        "smps_mpo_apply_batched_caps": (c_int, [vp, c_int, POINTER(vp), POINTER(vp), ip, POINTER(Strategy),
+                                                POINTER(vp), dp]),
         "smps_ctx_destroy": (c_int, [vp]),
         "smps_last_error": (ctypes.c_char_p, [vp]),
         "smps_ctx_workspace_bytes": (c_int, [vp, POINTER(c_size_t)]),
@@ -497,13 +500,19 @@ class Context:
         self._check(self.lib.smps_zscprod(self.h, a.h, b.h, byref(re), byref(im)))
         return complex(re.value, im.value)
 
-    def mpo_apply_batched(self, Us, vs, st: Strategy):
+    def mpo_apply_batched(self, Us, vs, st: Strategy, max_bonds=None):
+        """Batched apply; max_bonds (one cap per problem) replaces st.max_bond."""
         n = len(vs)
         uh = (c_void_p * n)(*[u.h for u in Us])
         vh = (c_void_p * n)(*[v.h for v in vs])
         outs = (c_void_p * n)()
         errs = (c_double * n)()
-        self._check(self.lib.smps_mpo_apply_batched(self.h, n, uh, vh, byref(st), outs, errs))
+        if max_bonds is None:
+            rc = self.lib.smps_mpo_apply_batched(self.h, n, uh, vh, byref(st), outs, errs)
+        else:
+            caps = (c_int * n)(*[int(x) for x in max_bonds])
+            rc = self.lib.smps_mpo_apply_batched_caps(self.h, n, uh, vh, caps, byref(st), outs, errs)
+        self._check(rc)
         return [MPS(self, c_void_p(outs[i])) for i in range(n)], list(errs)
 
     def scprod(self, a: MPS, b: MPS) -> float:
@@ -580,12 +589,13 @@ class Context:
             raise SmpsError(rc, self.lib.smps_last_error(self.h).decode(), info.as_dict())
         return info.as_dict()
 
-    def plan_apply_batched(self, Us, vs, st: Strategy) -> dict:
+    def plan_apply_batched(self, Us, vs, st: Strategy, max_bonds=None) -> dict:
         n = len(vs)
         uh = (c_void_p * n)(*[u.h for u in Us])
         vh = (c_void_p * n)(*[v.h for v in vs])
+        caps = None if max_bonds is None else (c_int * n)(*[int(x) for x in max_bonds])
         info = PlanInfo()
-        rc = self.lib.smps_plan_apply_batched(self.h, n, uh, vh, byref(st), byref(info))
+        rc = self.lib.smps_plan_apply_batched(self.h, n, uh, vh, caps, byref(st), byref(info))
         if rc != OK:
             raise SmpsError(rc, self.lib.smps_last_error(self.h).decode(), info.as_dict())
         return info.as_dict()

@@ -791,19 +791,33 @@ int smps_dmrg(smps_ctx* c, const smps_mpo* H, const smps_mps* guess, const smps_
     return run_dmrg(c, H, guess, *st, krylov_dim, out, energy);
 }
 
-int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                           const smps_strategy* st, smps_mps** out, double* trunc_err) {
-    if (!c) return SMPS_EINVAL;
-    if (n < 0 || (n > 0 && (!U || !v || !out))) return fail(c, SMPS_EINVAL, "bad batch arguments");
-    for (int i = 0; i < n; ++i) out[i] = nullptr;
+static int check_batch(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                       const int* max_bonds, const smps_strategy* st) {
+    if (n < 0 || (n > 0 && (!U || !v))) return fail(c, SMPS_EINVAL, "bad batch arguments");
     int rc = check_strategy(c, st);
     if (rc) return rc;
     for (int i = 0; i < n; ++i) {
         rc = check_pair(c, U[i], v[i]);
         if (rc) return rc;
+        if (max_bonds && max_bonds[i] < 1) return fail(c, SMPS_EINVAL, "max_bonds entries must be >= 1");
     }
+    return SMPS_OK;
+}
+
+int smps_mpo_apply_batched_caps(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                                const int* max_bonds, const smps_strategy* st, smps_mps** out, double* trunc_err) {
+    if (!c) return SMPS_EINVAL;
+    if (n > 0 && !out) return fail(c, SMPS_EINVAL, "bad batch arguments");
+    for (int i = 0; i < n; ++i) out[i] = nullptr;
+    int rc = check_batch(c, n, U, v, max_bonds, st);
+    if (rc) return rc;
     if (!c->planning) SMPS_HIP(c, hipSetDevice(c->device));
-    return run_apply_batched(c, n, U, v, *st, out, trunc_err);
+    return run_apply_batched(c, n, U, v, *st, max_bonds, out, trunc_err);
+}
+
+int smps_mpo_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
+                           const smps_strategy* st, smps_mps** out, double* trunc_err) {
+    return smps_mpo_apply_batched_caps(c, n, U, v, nullptr, st, out, trunc_err);
 }
 
 int smps_plan_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_strategy* st,
@@ -815,22 +829,17 @@ int smps_plan_apply(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smp
     if (rc) return rc;
     rc = check_strategy(c, st);
     if (rc) return rc;
-    return plan_apply(c, 1, &U, &v, *st, false, info);
+    return plan_apply(c, 1, &U, &v, *st, nullptr, false, info);
 }
 
 int smps_plan_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                            const smps_strategy* st, smps_plan_info* info) {
+                            const int* max_bonds, const smps_strategy* st, smps_plan_info* info) {
     if (!c) return SMPS_EINVAL;
     if (!info) return fail(c, SMPS_EINVAL, "info is NULL");
     *info = smps_plan_info{};
-    if (n < 0 || (n > 0 && (!U || !v))) return fail(c, SMPS_EINVAL, "bad batch arguments");
-    int rc = check_strategy(c, st);
+    int rc = check_batch(c, n, U, v, max_bonds, st);
     if (rc) return rc;
-    for (int i = 0; i < n; ++i) {
-        rc = check_pair(c, U[i], v[i]);
-        if (rc) return rc;
-    }
-    return plan_apply(c, n, U, v, *st, true, info);
+    return plan_apply(c, n, U, v, *st, max_bonds, true, info);
 }
 
 int smps_last_info(const smps_ctx* c, smps_apply_info* info) {

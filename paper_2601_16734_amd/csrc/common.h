@@ -168,11 +168,9 @@ hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max
                                        size_t shm, PanelQueueState* q, hipStream_t s);
 // Exact factorization.  Chooses the LDS-resident kernel when nvec_cap*len_cap
 // fits (or the Gram split when `work` is given and the size allows),
-// otherwise the blocked multi-workgroup path: one persistent team when
-// `queue` (PANEL_QUEUE_BYTES of device memory) is given, else one launch per
-// round with the sweeps driven from the host (`flags`: one device int).
-hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s,
-                         PanelQueueState* queue = nullptr);
+// otherwise the blocked multi-workgroup path, one launch per round with the
+// sweeps driven from the host (`flags`: one device int).
+hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s);
 hipError_t launch_gemm_batched(const GemmDesc* d_descs, int count, const GemmDesc& types, int M_cap, int N_cap,
                                hipStream_t s, int prec);
 hipError_t launch_left_mpo_batched(const LeftMpoDesc* arr, int count, const LeftMpoDesc& types, int a_cap,

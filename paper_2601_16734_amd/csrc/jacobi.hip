@@ -1065,8 +1065,7 @@ static hipError_t round_sweep_graph(const JacobiDesc& dd, int rounds, int ew, di
     return hipSuccess;
 }
 
-hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s,
-                         PanelQueueState* queue) {
+hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double* work, int* flags, hipStream_t s) {
     if (nvec_cap <= 0 || len_cap <= 0) return hipSuccess;
     // exact splits of short rows: the Gram / tridiagonal / divide-and-conquer
     // path when the caller provides its workspace
@@ -1088,21 +1087,6 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     hipLaunchKernelGGL(fro2_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
     hipGraphExec_t exec = nullptr;
     const PanelShape ps = panel_shape(len_cap);
-    if (queue && len_cap <= 1024 && ps.bs >= 1) {
-        // blocked path as one persistent team: every sweep on the device, no
-        // host round trip per sweep
-        jacobi_panel_params(nvec_cap, len_cap, &dd.bs, &dd.nblk);
-        const int P = dd.nblk / 2;
-        if (P > g_num_cu) return hipErrorInvalidValue;
-        hipError_t e = launch_zero_ints((int*)queue, (int)(PANEL_QUEUE_BYTES / sizeof(int)), s);
-        if (e != hipSuccess) return e;
-        launch_panel_persistent(ps, P, jacobi_panel_bytes(len_cap, dd.bs), s, dd, nullptr, 1, P, queue,
-                                ROUND_MAX_SWEEPS);
-        hipLaunchKernelGGL(jacobi_select_kernel, dim3(1), dim3(JT), 0, s, dd, nullptr);
-        const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
-        hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
-        return hipGetLastError();
-    }
     if (len_cap <= 1024 && ps.bs >= 1) {
         // blocked path: a tournament over blocks of rows, each block pair
         // orthogonalised in LDS (one inner sweep), one launch per round

@@ -133,12 +133,13 @@ int run_autotune(smps_ctx* c, const smps_mpo* U, const smps_mps* v, const smps_s
 hipError_t mlp_predict_device(smps_ctx* c, const float* feats_dev, int n, float* out_dev, hipStream_t s);
 bool mlp_ready(const smps_ctx* c);
 void batch_cache_free(smps_ctx* c);
+// max_bonds (nullable): per-problem bond caps replacing st.max_bond
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                      const smps_strategy& st, smps_mps** out, double* trunc_err);
+                      const smps_strategy& st, const int* max_bonds, smps_mps** out, double* trunc_err);
 // What an apply (n = 1) or a batched apply would allocate and enqueue; runs
 // on the host only (any context kind).
 int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v, const smps_strategy& st,
-               bool batched, smps_plan_info* info);
+               const int* max_bonds, bool batched, smps_plan_info* info);
 }  // namespace smps
 
 #define SMPS_HIP(c, expr)                                                                         \

@@ -1427,14 +1427,23 @@ void batch_cache_free(smps_ctx* c) {
     c->batch = nullptr;
 }
 
+// The strategy of every problem of a batch: the shared one, with the
+// problem's own bond cap when max_bonds is given.
+static std::vector<smps_strategy> batch_strategies(int n, const smps_strategy& st, const int* max_bonds) {
+    std::vector<smps_strategy> sts(n, st);
+    if (max_bonds)
+        for (int i = 0; i < n; ++i) sts[i].max_bond = max_bonds[i];
+    return sts;
+}
+
 // Plans of all problems of a batch in one workspace.
 static int plan_batch(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                      const smps_strategy& st, std::vector<Plan>& plans, Layout& lay) {
-    if (st.factorization != SMPS_FACT_SVD)
+                      const std::vector<smps_strategy>& sts, std::vector<Plan>& plans, Layout& lay) {
+    if (n > 0 && sts[0].factorization != SMPS_FACT_SVD)
         return fail(c, SMPS_EUNSUPPORTED, "the batched path uses the exact factorization only");
     plans.resize(n);
     for (int i = 0; i < n; ++i) {
-        plan_problem(plans[i], U[i], v[i], st, lay);
+        plan_problem(plans[i], U[i], v[i], sts[i], lay);
         if (plans[i].max_nvec > 2048)
             return fail(c, SMPS_EUNSUPPORTED, "two-site tensors with more than 2048 rows or columns are not supported");
     }
@@ -1445,13 +1454,13 @@ static int plan_batch(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
 // `base`, merged into batched launches (descriptors staged in da); *nodes is
 // the kernel count of the graph that would hold them.  Host only.
 static int record_batch(smps_ctx* c, const std::vector<Plan>& plans, const smps_mpo* const* U,
-                        const smps_mps* const* v, const smps_strategy& st, char* base, DescArena& da,
+                        const smps_mps* const* v, const std::vector<smps_strategy>& sts, char* base, DescArena& da,
                         std::vector<Launch>& launches, long long* nodes, long long* nops) {
     const int n = (int)plans.size();
     std::vector<std::vector<Op>> ops(n);
     long long total = 0;
     for (int i = 0; i < n; ++i) {
-        Enq q{plans[i], U[i], v[i], st, base, c->stream, (int*)(base + plans[i].o_dims)};
+        Enq q{plans[i], U[i], v[i], sts[i], base, c->stream, (int*)(base + plans[i].o_dims)};
         q.rec = &ops[i];
         hipError_t e = q.run();
         if (e != hipSuccess) return fail(c, SMPS_EHIP, std::string("recording failed at ") + q.where);
@@ -1493,7 +1502,7 @@ static GatherLayout append_gather(const std::vector<Plan>& plans, char* base, De
 }
 
 int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v, const smps_strategy& st,
-               bool batched, smps_plan_info* info) {
+               const int* max_bonds, bool batched, smps_plan_info* info) {
     char* const base = (char*)PLAN_ADDRESS_BASE;  // notional workspace: recorded, never dereferenced
     if (!batched) {
         Plan p;
@@ -1511,16 +1520,17 @@ int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* con
         return check_workspace_limit(c, lay.total);
     }
     if (n == 0) return SMPS_OK;
+    const std::vector<smps_strategy> sts = batch_strategies(n, st, max_bonds);
     std::vector<Plan> plans;
     Layout lay;
-    int rc = plan_batch(c, n, U, v, st, plans, lay);
+    int rc = plan_batch(c, n, U, v, sts, plans, lay);
     if (rc != SMPS_OK) return rc;
     info->workspace_bytes = lay.total;
     for (const Plan& p : plans) info->steps += p.steps;
     DescArena da;
     std::vector<Launch> launches;
     long long nodes = 0, nops = 0;
-    rc = record_batch(c, plans, U, v, st, base, da, launches, &nodes, &nops);
+    rc = record_batch(c, plans, U, v, sts, base, da, launches, &nodes, &nops);
     if (rc != SMPS_OK) return rc;
     append_gather(plans, base, da);
     info->operations = nops;
@@ -1533,14 +1543,15 @@ int plan_apply(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* con
 }
 
 int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_mps* const* v,
-                      const smps_strategy& st, smps_mps** out, double* trunc_err) {
+                      const smps_strategy& st, const int* max_bonds, smps_mps** out, double* trunc_err) {
     if (n == 0) return st.factorization == SMPS_FACT_SVD
                            ? SMPS_OK
                            : fail(c, SMPS_EUNSUPPORTED, "the batched path uses the exact factorization only");
     // ---- plans of all problems in one workspace
+    const std::vector<smps_strategy> sts = batch_strategies(n, st, max_bonds);
     std::vector<Plan> plans;
     Layout lay;
-    int rc = plan_batch(c, n, U, v, st, plans, lay);
+    int rc = plan_batch(c, n, U, v, sts, plans, lay);
     if (rc != SMPS_OK) return rc;
     rc = ensure_arena(c, lay.total);
     if (rc != SMPS_OK) return rc;
@@ -1556,6 +1567,7 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
     }
     const int* sp = (const int*)&st;
     for (size_t i = 0; i < sizeof(st) / sizeof(int); ++i) key.push_back((const void*)(uintptr_t)(unsigned)sp[i]);
+    for (int i = 0; i < n; ++i) key.push_back((const void*)(uintptr_t)(unsigned)sts[i].max_bond);
     BatchCache* bc = (BatchCache*)c->batch;
     if (!bc || bc->key != key) {
         batch_cache_free(c);
@@ -1565,7 +1577,7 @@ int run_apply_batched(smps_ctx* c, int n, const smps_mpo* const* U, const smps_m
         DescArena da;
         std::vector<Launch> launches;
         long long nodes = 0;
-        rc = record_batch(c, plans, U, v, st, c->arena, da, launches, &nodes, nullptr);
+        rc = record_batch(c, plans, U, v, sts, c->arena, da, launches, &nodes, nullptr);
         if (rc == SMPS_OK && nodes > MAX_GRAPH_KERNELS) rc = refuse_graph(c, nodes);
         if (rc != SMPS_OK) {
             batch_cache_free(c);

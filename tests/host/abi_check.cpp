@@ -123,7 +123,7 @@ int main() {
             }
             if (!read_strategy(st)) return 2;
             smps_plan_info in{};
-            print_info(smps_plan_apply_batched(C(a), n, us.data(), vs.data(), &st, &in), in);
+            print_info(smps_plan_apply_batched(C(a), n, us.data(), vs.data(), nullptr, &st, &in), in);
         } else if (c == "destroy_ctx") {
             if (std::scanf("%d", &a) != 1) return 2;
             std::printf("rc %d\n", smps_ctx_destroy(C(a)));

@@ -206,6 +206,24 @@ def test_the_512_chain_batch_plans_within_the_graph_limit(pctx):
     assert total_steps == sum(8 * (w.meta["n"] - 1) for w in synth.workload_batch(0))
 
 
+def test_the_512_chain_batch_is_one_graph_with_per_chain_caps(pctx):
+    Us, vs, caps = [], [], []
+    for w in synth.workload_batch(0):
+        phys = [t.shape[1] for t in w.mps]
+        Us.append(pctx.mpo_zeros(phys, phys, [t.shape[0] for t in w.mpo] + [1]))
+        vs.append(pctx.mps_zeros(phys, [t.shape[0] for t in w.mps] + [1]))
+        caps.append(w.max_bond)
+    st = B.strategy(128, 1e-10, sweeps=4)
+    info = pctx.plan_apply_batched(Us, vs, st, max_bonds=caps)
+    assert info["steps"] == sum(8 * (w.meta["n"] - 1) for w in synth.workload_batch(0))
+    # steps of equal position share launches across all 512 chains
+    assert info["graph_kernels"] < 10000
+    bad = list(caps)
+    bad[7] = 0
+    assert code_of(pctx.plan_apply_batched, Us, vs, st, bad)[0] == B.EINVAL
+    assert code_of(pctx.mpo_apply_batched, Us, vs, st, bad)[0] == B.EINVAL
+
+
 # ---------------------------------------------------------------- the sanitized build
 
 def strategy_line(max_bond, tol=1e-10, mode=0, sweeps=4, prec=0, fact=0):
