@@ -39,6 +39,9 @@ PHILOX_W = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
 SKETCH_KEY = (0x0260116734000001, 0x00000000005EE95D)
 OVERSAMPLE = 16
 POWER_ITERS = 0
+# the learned rank is raised by this factor before oversampling (a sketch
+# below the rank is refused and redone exactly; one above it costs columns)
+PREDICT_MARGIN = 1.25
 M64 = (1 << 64) - 1
 
 
@@ -166,7 +169,7 @@ class SketchedSplit:
     """Split hook for oracle.mps.apply_simplify that follows the randomized
     factorization schedule.  The first left-to-right pass is exact.  Later
     steps predict the rank r_hat from the bond's previous split: the kept
-    rank there (predictor None) or ceil(exp(predictor(features))) clipped to
+    rank there (predictor None) or ceil(1.25 exp(predictor(features))) clipped to
     [1, min(max_bond, m, n)]; r_hat at that cap means the exact SVD.  With
     fixed=True there is no estimate: r_hat = min(max_bond, m, n).  A sketch
     k = r_hat + p of at least min(m, n) rows means the exact SVD.  kinds[step] records
@@ -188,7 +191,7 @@ class SketchedSplit:
         else:
             from oracle.mlp import features
             lr = min(30.0, max(0.0, float(self.predictor(features(spectrum)))))
-            rhat = int(min(lim, np.ceil(np.exp(lr))))
+            rhat = int(min(lim, np.ceil(PREDICT_MARGIN * np.exp(lr))))
         rhat = max(1, rhat)
         if rhat >= lim:
             return 0

@@ -226,4 +226,6 @@ hipError_t launch_scale_rows(double* W, const double* sigma, const int* dims, Di
                              hipStream_t s);
 hipError_t launch_identity(double* B, const int* dims, DimExpr n, int cap, hipStream_t s);
 constexpr int RSVD_OVERSAMPLE = 16;
+// factor on the rank predicted by the learned model before oversampling
+constexpr double RSVD_PREDICT_MARGIN = 1.25;
 }  // namespace smps

@@ -42,7 +42,8 @@ def run(ctx, mps, mpo, max_bond, tol, sweeps, fact):
 @pytest.mark.parametrize("fact", [B.FACT_RSVD_MLP, B.FACT_RSVD_PREV, B.FACT_RSVD_FIXED])
 def test_randomized_schedule_matches_oracle(ctx, fact):
     mps, mpo = decaying_case(16, 64, (3.0, 6.0), 1)
-    pred = constant_predictor(ctx, 24.5)
+    # a prediction that the sizing margin raises to 25 (+ oversampling)
+    pred = constant_predictor(ctx, 24.5 / orsvd.PREDICT_MARGIN)
     # the cap-sized sketch needs a cap below the bulk matrix size (ranks stay ~25)
     fixed = fact == B.FACT_RSVD_FIXED
     cap, least = (32, 6) if fixed else (64, 10)
@@ -61,7 +62,7 @@ def test_randomized_schedule_matches_oracle(ctx, fact):
 
 
 def test_fallback_when_rank_is_underpredicted_matches_exact(ctx):
-    """Predicted rank 1 (sketch 17) on bonds of rank ~25: every randomized step
+    """Predicted rank 1 (sketch 18 after the margin) on bonds of rank ~25: every randomized step
     is rejected and replaced by the exact SVD.  The exact mode factorizes the
     steps whose needed side is the shorter one with accumulated rotations (the
     randomized modes keep one orientation), so the two agree to rounding, with
@@ -81,7 +82,8 @@ def test_fallback_when_rank_is_underpredicted_matches_exact(ctx):
 
 def test_rejections_match_oracle_with_random_operator(ctx):
     mps, mpo = decaying_case(14, 32, (3.0, 6.0), 2)
-    pred = constant_predictor(ctx, 18.5)
+    # sized to 19 (+ oversampling) after the margin: below the ranks the random operator produces
+    pred = constant_predictor(ctx, 18.5 / orsvd.PREDICT_MARGIN)
     hook = orsvd.SketchedSplit(32, 1e-10, predictor=pred)
     ref = om.apply_simplify(mpo, mps, 32, 1e-10, sweeps=2, split_hook=hook)
     got, info, kinds, _ = run(ctx, mps, mpo, 32, 1e-10, 2, B.FACT_RSVD_MLP)

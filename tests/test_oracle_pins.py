@@ -499,7 +499,8 @@ def test_sketched_sweep_matches_exact_sweep_when_sketches_are_accepted():
     # the cap-sized sketch needs a cap below the matrix size: 32 (ranks stay
     # ~25; only the bulk matrices, 49 or more on both sides, are sketched)
     capped = apply_simplify(mpo, mps, 32, 1e-10, sweeps=2)
-    for cap, ref, kw, least in ((64, exact, {"predictor": lambda f: np.log(24.5)}, 10),
+    # (a constant prediction sized so that the margin brings the sketch to 25 + oversampling)
+    for cap, ref, kw, least in ((64, exact, {"predictor": lambda f: np.log(24.5 / rsvd.PREDICT_MARGIN)}, 10),
                                 (64, exact, {"predictor": None}, 10), (32, capped, {"fixed": True}, 6)):
         hook = rsvd.SketchedSplit(cap, 1e-10, **kw)
         got = apply_simplify(mpo, mps, cap, 1e-10, sweeps=2, split_hook=hook)
