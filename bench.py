@@ -938,7 +938,11 @@ def main():
         prof_out, _ = ctx.mpo_apply(U, v, st)
         fact_ms, fact_n = ctx.kernel_time(0)
         bulk_ms, bulk_n = ctx.kernel_time(2)
+        cat = {c: ctx.kernel_time(c)[0] for c in (1, 3, 4, 5, 6)}
         ctx.set_profiling(False)
+        phases = {"factorization": fact_ms, "x_tensors": cat[3], "theta_products": cat[4],
+                  "environment_updates": cat[5], "other_contractions": cat[1] - cat[3] - cat[4] - cat[5],
+                  "other_launches": cat[6]}
         prof_out.destroy()
         contr_ms = max(1e-9, ms - fact_ms)
         peak, issue = MFMA_PEAK.get(prec, (78.6, 1))
@@ -948,6 +952,7 @@ def main():
                "factorization_ms_per_step": fact_ms,
                "factorization_launches_per_step": fact_n,
                "bulk_split_ms_avg": bulk_ms / max(1, bulk_n), "bulk_splits_per_step": bulk_n,
+               "phase_kernel_ms_per_step": phases,
                "norm": info["norm"],
                "contraction_tflops": cflops / (contr_ms * 1e-3) / 1e12,
                "contraction_mfma_frac": issue * cflops / (contr_ms * 1e-3) / 1e12 / peak}

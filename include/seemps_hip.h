@@ -152,11 +152,20 @@ int smps_ctx_set_workspace_limit(smps_ctx *ctx, size_t bytes);
  * SMPS_EINVAL. */
 enum { SMPS_SPLIT_AUTO = 0, SMPS_SPLIT_JACOBI = 1, SMPS_SPLIT_GRAM = 2 };
 int smps_ctx_set_split(smps_ctx *ctx, int method);
-/* Kernel timing with HIP events recorded on the context stream around every
-   launch of a category (0 = every factorization of the single-problem sweep,
-   1 = contractions, 2 = the factorizations of the largest square two-site
-   tensor of the run -- the bulk steps -- also counted in 0).  on != 0 enables
-   it and clears the counters; smps_ctx_kernel_time returns the accumulated
+/* Per-phase kernel timing of the single-problem sweep, with HIP events
+   recorded on the context stream around every launch (enabling it adds two
+   event records per launch).  Categories:
+     0 = factorizations (every split of the sweep),
+     1 = contractions (every GEMM and MPO-site launch),
+     2 = the splits of the largest square two-site tensor of the run (the
+         bulk steps; also in 0),
+     3 = contractions that build the X tensors of a sweep step (also in 1),
+     4 = the two-site products theta (also in 1),
+     5 = the environment updates after a split (also in 1),
+     6 = every other launch (copies, fills, bond bookkeeping, norms).
+   Contractions outside a sweep step (canonical form of the guess, warm-start
+   rotations, the final projection) count in 1 only.  on != 0 enables it and
+   clears the counters; smps_ctx_kernel_time returns the accumulated
    milliseconds and the number of timed launches of a category since then. */
 int smps_ctx_set_profiling(smps_ctx *ctx, int on);
 int smps_ctx_kernel_time(smps_ctx *ctx, int category, double *total_ms, long long *launches);

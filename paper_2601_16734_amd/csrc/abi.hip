@@ -144,12 +144,13 @@ int prof_begin(smps_ctx* c, hipStream_t s) {
 void prof_end(smps_ctx* c, hipStream_t s, int token, int category, int also) {
     if (token < 0) return;
     if (hipEventRecord(c->ev_pool[token + 1], s) != hipSuccess) return;
-    if (category >= 0 && category < 3) c->ev_pending[category].emplace_back(token, token + 1);
-    if (also >= 0 && also < 3 && also != category) c->ev_pending[also].emplace_back(token, token + 1);
+    const int n = smps_ctx::PROF_CATEGORIES;
+    if (category >= 0 && category < n) c->ev_pending[category].emplace_back(token, token + 1);
+    if (also >= 0 && also < n && also != category) c->ev_pending[also].emplace_back(token, token + 1);
 }
 
 void prof_collect(smps_ctx* c) {
-    for (int cat = 0; cat < 3; ++cat) {
+    for (int cat = 0; cat < smps_ctx::PROF_CATEGORIES; ++cat) {
         for (auto& pr : c->ev_pending[cat]) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]) == hipSuccess) {
@@ -336,7 +337,7 @@ int smps_ctx_set_profiling(smps_ctx* c, int on) {
     SMPS_HIP(c, hipStreamSynchronize(c->stream));
     prof_collect(c);
     c->profiling = on != 0;
-    for (int cat = 0; cat < 3; ++cat) {
+    for (int cat = 0; cat < smps_ctx::PROF_CATEGORIES; ++cat) {
         c->prof_ms[cat] = 0.0;
         c->prof_n[cat] = 0;
     }
@@ -344,7 +345,7 @@ int smps_ctx_set_profiling(smps_ctx* c, int on) {
 }
 
 int smps_ctx_kernel_time(smps_ctx* c, int category, double* total_ms, long long* launches) {
-    if (!c || category < 0 || category > 2) return SMPS_EINVAL;
+    if (!c || category < 0 || category >= smps_ctx::PROF_CATEGORIES) return SMPS_EINVAL;
     int rc = need_device(c);
     if (rc) return rc;
     SMPS_HIP(c, hipStreamSynchronize(c->stream));

@@ -48,10 +48,11 @@ struct smps_ctx {
     // optional per-category kernel timing (events recorded on the stream)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_pending[3];  // (start, stop) indices per category
+    static constexpr int PROF_CATEGORIES = 7;  // see smps_ctx_kernel_time
+    std::vector<std::pair<int, int>> ev_pending[PROF_CATEGORIES];  // (start, stop) indices per category
     int ev_used = 0;
-    double prof_ms[3] = {0.0, 0.0, 0.0};
-    long long prof_n[3] = {0, 0, 0};
+    double prof_ms[PROF_CATEGORIES] = {};
+    long long prof_n[PROF_CATEGORIES] = {};
 };
 
 struct smps_mps {

@@ -303,6 +303,8 @@ struct Enq {
     std::vector<Op>* rec = nullptr;  // record instead of launching
     mutable const char* where = "";
     mutable int cur_major = 0, cur_j = 0, cur_slot = 0;
+    // phase of the contractions being emitted (kernel timing categories 3-5, -1: none of them)
+    mutable int cur_phase = -1;
     // single path only: sweeps and steps actually run (early stop on sweep_tol),
     // the factorization log and the predicted log ranks of the current half-sweep
     mutable int sweeps_done = 0, steps_done = 0;
@@ -344,6 +346,18 @@ struct Enq {
             rec->push_back(std::move(op));
             return hipSuccess;
         }
+        if (op.kind != OP_JAC && ctx && ctx->profiling) {
+            // per-phase timing: contractions (category 1, and 3-5 by phase), the rest (6)
+            const bool contraction = op.kind == OP_GEMM || op.kind == OP_LEFT || op.kind == OP_RIGHT;
+            const int tok = prof_begin(ctx, s);
+            hipError_t e = launch_op(op);
+            prof_end(ctx, s, tok, contraction ? 1 : 6, contraction ? cur_phase : -1);
+            return e;
+        }
+        return launch_op(op);
+    }
+
+    hipError_t launch_op(const Op& op) const {
         switch (op.kind) {
             case OP_GEMM: return launch_gemm(op.g, op.cap0, op.cap1, 1, s, op.prec);
             case OP_LEFT: return launch_left_mpo(op.l, op.cap0, s);
@@ -829,13 +843,16 @@ struct Enq {
                 const bool acc = use_acc(c[k] * e[k], e[k + 1] * c[k + 2]);
                 // theta = sum_t w_t XL_t[k] XR_t[k+1] (one term: the plain product)
                 for (int t = 0; t < NT; ++t) {
+                    cur_phase = 3;
                     CK(build_XL(k, t));
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
+                    cur_phase = 4;
                     CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
                             ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, acc ? 0 : 1, c[k] * e[k], e[k + 1] * c[k + 2],
                             p.prec, wt(t), t ? 1.0 : 0.0));
                 }
                 const int mr = std::min(st.max_bond, c[k + 1]);
+                cur_phase = -1;  // the split and its warm-start rotation
                 // warm start (sw > 0): rotate by the right singular basis this bond
                 // produced in the previous right-to-left pass (identity when it was not full)
                 if (acc)
@@ -845,11 +862,13 @@ struct Enq {
                     CK(factor(k, step, sw > 0, rs_lr, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]),
                               e[k + 1] * c[k + 2], c[k] * e[k], at<double>(p.o_Q), mr));
                 // Lenv_t[k+1] = Q XL_t[k]
+                cur_phase = 5;
                 for (int t = 0; t < NT; ++t) {
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
                     CK(gemm(at(p.o_Q), T_F64, at(oXL(t, k)), p.et, at(oL(t, k + 1)), p.et, ddyn(k + 1), dconst(K),
                             ddyn(k, e[k]), 0, 0, 0, c[k + 1], K, p.prec));
                 }
+                cur_phase = -1;
                 ++step;
             }
             // bond k was last factorized in this sweep's left-to-right pass, at step 2 sw (L - 1) + k
@@ -861,13 +880,16 @@ struct Enq {
                 // accumulated rotations of theta^T's rows when those are the shorter side
                 const bool acc = use_acc(e[k + 1] * c[k + 2], c[k] * e[k]);
                 for (int t = 0; t < NT; ++t) {
+                    cur_phase = 3;
                     CK(build_XR(k + 1, at(oR(t, k + 2)), at(otmp(t)), at(oXR(t, k + 1)), p.et, p.prec, t));
                     const int K = Dm_(t)[k + 1] * chiv_(t)[k + 1];
+                    cur_phase = 4;
                     CK(gemm(at(oXL(t, k)), p.et, at(oXR(t, k + 1)), p.et, theta, T_F64, ddyn(k, e[k]),
                             ddyn(k + 2, e[k + 1]), dconst(K), 0, 0, acc ? 1 : 0, c[k] * e[k], e[k + 1] * c[k + 2],
                             p.prec, wt(t), t ? 1.0 : 0.0));
                 }
                 const int mr = std::min(st.max_bond, c[k + 1]);
+                cur_phase = -1;
                 // warm start from the left singular basis of this pass's left-to-right visit
                 if (acc)
                     CK(factor(k, step, sw > 0, rs, theta, ddyn(k + 2, e[k + 1]), ddyn(k, e[k]), e[k + 1] * c[k + 2],
@@ -875,8 +897,10 @@ struct Enq {
                 else
                     CK(factor(k, step, true, rs, theta, ddyn(k, e[k]), ddyn(k + 2, e[k + 1]), c[k] * e[k],
                               e[k + 1] * c[k + 2], at<double>(p.o_psi[k + 1]), mr));
+                cur_phase = 5;
                 for (int t = 0; t < NT; ++t)
                     CK(env_R(k + 1, at(oXR(t, k + 1)), at(oR(t, k + 1)), p.et, p.prec, t));
+                cur_phase = -1;
                 ++step;
             }
             sweeps_done = sw + 1;
