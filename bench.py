@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--c3-applies", type=int, default=3,
                     help="timed applies per precision of the L=100 chi=256 sub-record of the default run "
                          "(after one warm-up); 0 skips it")
+    ap.add_argument("--c4-steps", type=int, default=3,
+                    help="timed batched calls per precision of the 512-chain sub-record of the default run (0: skip)")
     ap.add_argument("--large", action="store_true",
                     help="only measure the L=100 chi=256 XXZ workload (4 sweeps, FP64 and mixed contractions, the "
                          "whole oracle as parity reference; several minutes) and print its JSON line")
@@ -832,6 +834,73 @@ def c3_subrecord(ctx, args, stream):
             "oracle_cpu_seconds": g.get("oracle_seconds")}
 
 
+def c4_subrecord(ctx, args, stream):
+    """The 512-chain QTT batch (n uniform in [8, 30], chi uniform in {4, ...,
+    128}, FP32 N(0, 1/chi) entries promoted to FP64, bond-3 Laplacian or bond-2
+    shift), every chain at its own cap, tol 1e-10, 4 sweeps, as one batched
+    call (one graph): per precision one capturing call and args.c4_steps timed
+    replays (HIP events on the stream, inputs resident), every chain of the
+    last result checked against the oracle's whole runs stored in tests/golden
+    (written by the oracle alone): final norm (1e-8 bar) and bonds."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2601_16734_amd import binding as B
+
+    with open(os.path.join(ROOT, "tests", "golden", "batch512_s4.json")) as fh:
+        g = json.load(fh)
+    ws = synth.workload_batch(0)
+    sweeps = g["sweeps"]
+    su = sum(sweeps * 2 * (w.meta["n"] - 1) for w in ws)
+    vs = [ctx.mps_create(w.mps, dtype=np.float32) for w in ws]
+    Us = [ctx.mpo_create(w.mpo) for w in ws]
+    caps = [w.max_bond for w in ws]
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        st = B.strategy(max(caps), 1e-10, sweeps=sweeps, precision=prec)
+        outs, _ = ctx.mpo_apply_batched(Us, vs, st, max_bonds=caps)  # capture + replay
+        for o in outs:
+            o.destroy()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, args.c4_steps)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            outs, _ = ctx.mpo_apply_batched(Us, vs, st, max_bonds=caps)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times.append(a.elapsed_time(b))
+            last = outs
+            if len(times) < max(1, args.c4_steps):
+                for o in outs:
+                    o.destroy()
+        errs, bonds_ok = [], 0
+        for o, ref in zip(last, g["chains"]):
+            errs.append(abs(ctx.norm(o) - ref["norm"]) / ref["norm"])
+            bonds_ok += list(o.shape()[1]) == ref["ranks"]
+            o.destroy()
+        errs = np.array(errs)
+        ms = float(np.median(times))
+        res[prec] = {"ms_per_call_median": ms, "ms_per_call_all": times, "site_updates_per_s": su / (ms * 1e-3),
+                     "rel_norm_err_max": float(errs.max()), "chains_within_1e-8": int(np.sum(errs <= 1e-8)),
+                     "chains_bonds_equal": int(bonds_ok),
+                     "parity_1e-8": bool(errs.max() <= 1e-8 and bonds_ok == len(ws))}
+        print(f"c4 sub-record: {prec} {su / (ms * 1e-3):.0f} site-updates/s, worst norm err {errs.max():.1e}",
+              file=sys.stderr, flush=True)
+    for h in vs + Us:
+        h.destroy()
+    fp64 = res["fp64"]["site_updates_per_s"]
+    ok = [p for p in ("fp32", "bf16x3") if res[p]["parity_1e-8"]]
+    best = max(ok, key=lambda p: res[p]["site_updates_per_s"]) if ok else None
+    return {"workload": "512 QTT chains, n uniform in [8,30], d=2, chi uniform in {4,...,128}, FP32 entries, bond-3 "
+                        "Laplacian or bond-2 shift MPO, max bond chi, tol 1e-10, 4 sweeps; one batched call, one graph",
+            "site_updates_per_call": su, "warmup": 1, "calls": max(1, args.c4_steps),
+            "parity_reference": "oracle whole run of every chain, tests/golden", "per_precision": res,
+            "best_mixed_at_parity": best,
+            "speedup_vs_fp64": (res[best]["site_updates_per_s"] / fp64) if best else None}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1017,6 +1086,8 @@ def main():
     }
     if args.c3_applies > 0:
         line["c3_xxz_L100_chi256"] = c3_subrecord(ctx, args, stream)
+    if args.c4_steps > 0:
+        line["c4_qtt512_batched"] = c4_subrecord(ctx, args, stream)
     print(json.dumps(line))
     ctx.close()
 
