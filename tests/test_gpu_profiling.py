@@ -1,6 +1,7 @@
-"""Per-phase kernel timing of the single-problem sweep (HIP events around
-every launch when profiling is on): the categories partition the launches as
-documented, and profiling changes no result."""
+"""Observability of the single-problem sweep: per-phase kernel timing (HIP
+events around every launch when profiling is on) partitions the launches as
+documented and changes no result; the same input run twice gives the same
+bits."""
 
 import pytest
 
@@ -39,3 +40,26 @@ def test_phase_timers_partition_the_launches(ctx):
     assert all(t[c][0] > 0 for c in range(7))
     for h in (out, ref, U, v):
         h.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_single_path_is_deterministic(ctx, precision):
+    # the same input twice gives the same bits: every reduction on the path
+    # (dot products, norms, tail sums, GEMM k order) has a fixed order
+    import numpy as np
+    w = synth.workload_random_mpo(0)
+    U, v = ctx.mpo_create(w.mpo), ctx.mps_create(w.mps)
+    st = B.strategy(w.max_bond, w.tol, sweeps=2, precision=precision)
+    runs = []
+    for _ in range(2):
+        out, err = ctx.mpo_apply(U, v, st)
+        deltas, ranks, _ = ctx.last_log()
+        runs.append((out.read(), err, np.array(deltas), list(ranks)))
+        out.destroy()
+    (a, ea, da, ra), (b, eb, db, rb) = runs
+    assert ea == eb and ra == rb
+    np.testing.assert_array_equal(da, db)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    U.destroy()
+    v.destroy()
