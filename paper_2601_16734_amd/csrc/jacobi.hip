@@ -359,6 +359,166 @@ static int elems_for(int len_cap) {
     return 0;
 }
 
+// ---- completion of a rank-deficient warm-start basis -----------------------
+// The basis handed to the next visit of a bond must be a complete orthogonal
+// matrix (it pre-rotates that visit's vectors).  When the split's vectors do
+// not span the whole space (numerically rank-deficient two-site tensors, or
+// fewer vectors than their length), the normalised vectors of the nonzero
+// values fill rows 0..m-1 and rows m..len-1 are completed here: pivoted
+// Gram-Schmidt on the unit vectors, each step taking the unit vector with the
+// largest squared component p_j outside the current span (at least
+// (len - k)/len at step k, since the p_j sum to len - k), with a second pass
+// whenever the first leaves less than half of it.  B is len x len in global
+// memory, read and written by this workgroup only.
+
+__device__ double block_sum(double x, double* redv) {
+    x = wave_sum(x);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) redv[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += redv[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ int block_argmax(const double* p, int n, double* redv, int* redi) {
+    double best = -2.0;
+    int bi = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        if (p[j] > best) {
+            best = p[j];
+            bi = j;
+        }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        redv[w] = best;
+        redi[w] = bi;
+    }
+    __syncthreads();
+    double b = redv[0];
+    int r = redi[0];
+    for (int i = 1; i < nw; ++i)
+        if (redv[i] > b || (redv[i] == b && redi[i] < r)) {
+            b = redv[i];
+            r = redi[i];
+        }
+    __syncthreads();
+    return r;
+}
+
+// A basis is completed when the split has at least as many vectors as their
+// length (it would be complete at full rank: rank-deficient two-site tensors)
+// and the rows have at least COMPLETE_MIN_LEN elements; otherwise it stays the
+// identity.  Below that length the completion (a few barriers per vector)
+// costs more than the cold sweeps it saves (measured on the 512-chain batch:
+// 64-element rows 100 -> 600 us per split, 256-element rows 7.8 -> 3.7 ms);
+// with fewer vectors than their length the bond's next visit takes its warm
+// start from accumulated rotations instead (n=20 chi=64: 8 ms per apply spent
+// on completions nobody read).
+constexpr int COMPLETE_MIN_LEN = 128;
+__device__ __forceinline__ bool completes_basis(int nv, int len) { return nv >= len && len >= COMPLETE_MIN_LEN; }
+
+// LDS doubles complete_basis needs: p, coefficients, reductions and the
+// sliced partial sums (at most one per thread of a 1024-thread workgroup).
+__host__ __device__ constexpr size_t complete_lds_doubles(int len) {
+    return (size_t)len * 2 + 64 + 1024;
+}
+
+// r[l] = base[l] - sum_{i<k} coef[i] B[i][l] for all l, the k-sum split over
+// the threads beyond len (slices of i, combined through LDS in slice order, so
+// the result does not depend on timing); returns this thread's part of |r|^2.
+__device__ double project_out(const double* B, int len, int k, const double* coef, double* r, int piv,
+                              bool from_unit, double* part) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ns = nt >= 2 * len ? min(nt / len, 16) : 1;  // slices of the i range
+    const int sl = tid / len, l0 = tid - sl * len;
+    double acc = 0.0;
+    if (ns > 1) {
+        if (sl < ns) {
+            const int i0 = (int)((long long)k * sl / ns), i1 = (int)((long long)k * (sl + 1) / ns);
+            for (int i = i0; i < i1; ++i) acc = fma(coef[i], B[(size_t)i * len + l0], acc);
+            part[sl * len + l0] = acc;
+        }
+        __syncthreads();
+        double nrm = 0.0;
+        if (tid < len) {
+            double a = 0.0;
+            for (int x = 0; x < ns; ++x) a += part[x * len + tid];
+            const double v = (from_unit ? (tid == piv ? 1.0 : 0.0) : r[tid]) - a;
+            r[tid] = v;
+            nrm = v * v;
+        }
+        __syncthreads();
+        return nrm;
+    }
+    double nrm = 0.0;
+    for (int l = tid; l < len; l += nt) {
+        double v = from_unit ? (l == piv ? 1.0 : 0.0) : r[l];
+        for (int i = 0; i < k; ++i) v = fma(-coef[i], B[(size_t)i * len + l], v);
+        r[l] = v;
+        nrm = fma(v, v, nrm);
+    }
+    return nrm;
+}
+
+__device__ void complete_basis(double* B, int len, int m, double* scratch) {
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, w = tid >> 6, nw = (nt + 63) >> 6;
+    double* p = scratch;          // len
+    double* coef = p + len;       // len
+    double* redv = coef + len;    // 32
+    int* redi = (int*)(redv + 32);
+    double* part = redv + 64;     // slices x len <= blockDim.x doubles
+    for (int j = tid; j < len; j += nt) {
+        double a = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double b = B[(size_t)i * len + j];
+            a = fma(b, b, a);
+        }
+        p[j] = 1.0 - a;
+    }
+    __syncthreads();
+    for (int k = m; k < len; ++k) {
+        const int piv = block_argmax(p, len, redv, redi);
+        const double pk = p[piv];
+        for (int i = tid; i < k; i += nt) coef[i] = B[(size_t)i * len + piv];
+        __syncthreads();
+        double* r = B + (size_t)k * len;
+        double n2 = block_sum(project_out(B, len, k, coef, r, piv, true, part), redv);
+        __threadfence_block();
+        if (n2 < 0.5 * pk) {
+            // second pass: coefficients against the same rows
+            for (int i = w; i < k; i += nw) {
+                double a = 0.0;
+                for (int l = lane; l < len; l += 64) a = fma(B[(size_t)i * len + l], r[l], a);
+                a = wave_sum(a);
+                if (lane == 0) coef[i] = a;
+            }
+            __syncthreads();
+            n2 = block_sum(project_out(B, len, k, coef, r, piv, false, part), redv);
+            __threadfence_block();
+        }
+        const double inv = 1.0 / sqrt(n2);
+        for (int l = tid; l < len; l += nt) {
+            const double v = r[l] * inv;
+            r[l] = v;
+            p[l] -= v * v;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) p[piv] = -1.0;
+        __syncthreads();
+    }
+}
+
 // Kept rows: Q[i] = W[perm[i]] / s_i (a zero vector only occurs when the
 // whole matrix is zero and one row is kept: it becomes the first unit vector).
 __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, const double* sig_sorted,
@@ -381,13 +541,24 @@ __device__ void jacobi_write_rows(const double* W, int nv, int len, int ld, cons
         Q[e] = s > 0.0 ? W[(size_t)perm[i] * ld + l] / s : (l == i ? 1.0 : 0.0);
     }
     if (!basis) return;
-    // len x len basis for the next visit of this bond: every normalised vector
-    // when they span the whole space, else the identity (no warm start)
-    const bool full = nv >= len && sig_sorted[len - 1] > 0.0;
+    // len x len basis for the next visit of this bond: the normalised vectors
+    // of the nonzero values (rows of zero values are completed afterwards by
+    // complete_basis)
+    const int nz = nv < len ? nv : len;
     for (size_t e = threadIdx.x; e < (size_t)len * len; e += blockDim.x) {
         const int i = (int)(e / len), l = (int)(e % len);
-        basis[e] = full ? W[(size_t)perm[i] * ld + l] / sig_sorted[i] : (l == i ? 1.0 : 0.0);
+        const bool live = i < nz && sig_sorted[i] > 0.0;
+        basis[e] = live ? W[(size_t)perm[i] * ld + l] / sig_sorted[i] : 0.0;
     }
+}
+
+// Rows of the basis that jacobi_write_rows filled (the nonzero values among
+// the first min(nv, len) sorted ones).
+__device__ int basis_rows(const double* sig_sorted, int nv, int len) {
+    const int nz = nv < len ? nv : len;
+    int m = 0;
+    while (m < nz && sig_sorted[m] > 0.0) ++m;
+    return m;
 }
 
 template <int E, bool ACC>
@@ -451,6 +622,16 @@ __global__ __launch_bounds__(lds_threads(E)) void jacobi_lds_kernel(JacobiDesc d
     if (ACC && d.acc_tag) {
         for (int e = tid; e < nv * nv; e += LDS_NT) d.acc_basis[e] = Jw[e];
         if (tid == 0) *d.acc_tag = 2 * nv + d.acc_dir + 1;
+    }
+    if (!ACC && d.basis) {
+        // complete a rank-deficient basis; W is free now and holds the scratch
+        const int m = basis_rows(sig_sorted, nv, len);
+        __threadfence_block();
+        __syncthreads();
+        if (m < len && completes_basis(nv, len) && (size_t)nv * ld >= complete_lds_doubles(len))
+            complete_basis(d.basis, len, m, W);
+        else if (m < len)
+            for (int e = tid; e < len * len; e += LDS_NT) d.basis[e] = (e / len == e % len) ? 1.0 : 0.0;
     }
 }
 
@@ -730,12 +911,29 @@ __global__ __launch_bounds__(256) void jacobi_write_kernel(JacobiDesc d0, const 
             d.Q[(size_t)i * len + l] = s > 0.0 ? w[l] / s : (l == i ? 1.0 : 0.0);
     }
     if (d.basis && i < len) {
-        const bool full = nv >= len && d.sigma[len - 1] > 0.0;
-        const double s = full ? d.sigma[i] : 0.0;
-        const double* w = d.X + (size_t)(full ? d.perm[i] : 0) * len;
+        // normalised vectors of the nonzero values; jacobi_complete_kernel fills the rest
+        const bool live = i < nv && d.sigma[i] > 0.0;
+        const double s = live ? d.sigma[i] : 1.0;
+        const double* w = d.X + (size_t)(live ? d.perm[i] : 0) * len;
         for (int l = blockIdx.x * 256 + threadIdx.x; l < len; l += gridDim.x * 256)
-            d.basis[(size_t)i * len + l] = full ? w[l] / s : (l == i ? 1.0 : 0.0);
+            d.basis[(size_t)i * len + l] = live ? w[l] / s : 0.0;
     }
+}
+
+// Completion of the blocked paths' warm-start basis (one workgroup per
+// factorization; dynamic LDS: complete_lds_doubles(len) doubles).
+__global__ __launch_bounds__(1024) void jacobi_complete_kernel(JacobiDesc d0, const JacobiDesc* arr) {
+    extern __shared__ double sm[];
+    const JacobiDesc d = arr ? arr[blockIdx.x] : d0;
+    if (!d.basis) return;
+    const int nv = eval_dim(d.dims_in, d.nvec), len = eval_dim(d.dims_in, d.len);
+    const int m = basis_rows(d.sigma, nv, len);
+    if (m >= len) return;
+    if (completes_basis(nv, len)) {
+        complete_basis(d.basis, len, m, sm);
+        return;
+    }
+    for (int e = threadIdx.x; e < len * len; e += blockDim.x) d.basis[e] = (e / len == e % len) ? 1.0 : 0.0;
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
@@ -801,7 +999,8 @@ hipError_t jacobi_init(int device) {
                              (const void*)jacobi_panel_persistent_kernel<8>,
                              (const void*)jacobi_panel_persistent_kernel<16>,
                              (const void*)jacobi_panel_persistent_kernel<16, 32>,
-                             (const void*)jacobi_panel_persistent_kernel<16, 64>};
+                             (const void*)jacobi_panel_persistent_kernel<16, 64>,
+                             (const void*)jacobi_complete_kernel};
     for (const void* f : kernels) {
         hipFuncAttributes a{};
         if (hipFuncGetAttributes(&a, f) == hipSuccess && a.sharedSizeBytes > stat) stat = a.sharedSizeBytes;
@@ -1124,6 +1323,9 @@ hipError_t launch_jacobi(const JacobiDesc& d, int nvec_cap, int len_cap, double*
     if (dd.log_sweeps) hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, dd.log_sweeps, sweep);
     const int rows = d.basis ? (nvec_cap > len_cap ? nvec_cap : len_cap) : nvec_cap;
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, rows, 1), dim3(256), 0, s, dd, nullptr);
+    if (dd.basis)
+        hipLaunchKernelGGL(jacobi_complete_kernel, dim3(1), dim3(1024), sizeof(double) * complete_lds_doubles(len_cap),
+                           s, dd, nullptr);
     return hipGetLastError();
 }
 
@@ -1144,8 +1346,8 @@ int jacobi_panel_teams(int count, int max_pairs) {
 }
 
 // Every descriptor carries bs / nblk / fro2; q is the launch's queue state
-// (PANEL_QUEUE_BYTES).  Five kernels whatever the sweep count: queue reset,
-// norms, the persistent sweeps, selection, write-back.
+// (PANEL_QUEUE_BYTES).  Six kernels whatever the sweep count: queue reset,
+// norms, the persistent sweeps, selection, write-back, basis completion.
 hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max_pairs, int max_rows, int len_cap,
                                        size_t shm, PanelQueueState* q, hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -1161,6 +1363,8 @@ hipError_t launch_jacobi_panel_batched(const JacobiDesc* arr, int count, int max
     hipLaunchKernelGGL(jacobi_select_kernel, dim3(count), dim3(JT), 0, s, none, arr);
     hipLaunchKernelGGL(jacobi_write_kernel, dim3((len_cap + 255) / 256, max_rows, count), dim3(256), 0, s, none,
                        arr);
+    hipLaunchKernelGGL(jacobi_complete_kernel, dim3(count), dim3(1024), sizeof(double) * complete_lds_doubles(len_cap),
+                       s, none, arr);
     return hipGetLastError();
 }
 

@@ -1398,7 +1398,7 @@ static long long graph_kernels(const std::vector<Launch>& ls) {
     long long n = 1;  // the gather
     for (const Launch& l : ls) {
         if (l.kind == OP_JAC && l.panel)
-            n += 5;  // queue reset, norms, persistent sweeps, selection, write-back
+            n += 6;  // queue reset, norms, persistent sweeps, selection, write-back, basis completion
         else
             n += 2;
     }
