@@ -92,32 +92,40 @@ __device__ __forceinline__ double group_sum(double x) {
 // Rutishauser's rotation for a pair with squared norms a, b and dot product c:
 // t = sgn(z) / (|z| + sqrt(1 + z^2)), z = (b - a) / 2c, written as
 // t = sgn(b - a) 2c / (|b - a| + sqrt((b - a)^2 + 4c^2)).  That form is
-// homogeneous of degree 0, so both terms are first scaled by an approximate
-// 1 / max(|b - a|, |2c|) (no overflow or underflow), and the square root and
-// the quotient use the hardware approximations with one Newton step each.
-// cs = 1 / sqrt(1 + t^2) gets its own Newton step so that cs^2 + sn^2 = 1 to
-// rounding: that, not the exact angle, keeps the transformation orthogonal.
+// homogeneous of degree 0: it is evaluated as it stands when (b - a)^2 + 4c^2
+// lies between 2^-900 and 2^900, and otherwise (a rare branch) after scaling
+// both terms by an approximate 1 / max(|b - a|, |2c|), so nothing under- or
+// overflows; the square root and the quotient use the hardware
+// approximations with one Newton step each.  cs = 1 / sqrt(1 + t^2) gets its
+// own Newton step so that cs^2 + sn^2 = 1 to rounding: that, not the exact
+// angle, keeps the transformation orthogonal.
 __device__ __forceinline__ void jacobi_rotation(double a, double b, double c, double& cs, double& sn, double& t) {
-    const double d = b - a, c2 = c + c;
-    const double r = __builtin_amdgcn_rcp(fmax(fabs(d), fabs(c2)));
-    const double dn = d * r, cn = c2 * r;
-    const double hh = fma(dn, dn, cn * cn);
+    double dn = b - a, cn = c + c;
+    double hh = fma(dn, dn, cn * cn);
+    if (!(hh > 0x1p-900 && hh < 0x1p900)) {
+        asm volatile("");  // keeps the rare branch a branch (not evaluated on every pair)
+        const double r = __builtin_amdgcn_rcp(fmax(fabs(dn), fabs(cn)));
+        dn *= r;
+        cn *= r;
+        hh = fma(dn, dn, cn * cn);
+    }
     double rs = __builtin_amdgcn_rsq(hh);
     rs = rs * fma(-0.5 * hh * rs, rs, 1.5);
     const double den = fma(hh, rs, fabs(dn));
     double rc = __builtin_amdgcn_rcp(den);
     rc = rc * fma(-den, rc, 2.0);
-    t = (d >= 0.0 ? cn : -cn) * rc;
+    t = (dn >= 0.0 ? cn : -cn) * rc;
     const double h = fma(t, t, 1.0);
     cs = __builtin_amdgcn_rsq(h);
     cs = cs * fma(-0.5 * h * cs, cs, 1.5);
     sn = cs * t;
 }
 
-// |c| > tol sqrt(a b); the square roots only set a threshold, so the hardware
-// reciprocal square roots are used as they are.
+// |c| > tol sqrt(a b), compared squared: c^2 > (tol a)(tol b), three products
+// instead of two square roots (a, b are positive; c^2 overflowing to inf still
+// answers correctly, and tol <= 2^-52 * 2048 keeps tol a finite).
 __device__ __forceinline__ bool jacobi_needs_rotation(double a, double b, double c, double tol) {
-    return fabs(c) > tol * (a * __builtin_amdgcn_rsq(a)) * (b * __builtin_amdgcn_rsq(b));
+    return c * c > (tol * a) * (tol * b);
 }
 
 // Copy nrows rows of len doubles from global memory (row j starts at
