@@ -88,3 +88,30 @@ def test_blocked_factorizations_vs_whole_oracle(ctx):
     assert 1.0 - abs(ab) / math.sqrt(om.scprod(got, got) * om.scprod(ref.mps, ref.mps)) <= 1e-10
     assert abs(err - ref.error_bound) <= 1e-6 * ref.error_bound + 1e-12
     check_state(ctx, out, info)
+
+
+def test_round_kernel_rows_beyond_1024_vs_whole_oracle(ctx):
+    # L=3, d=40, chi=40, bond cap 24: the two-site tensors are 40 x 1600 and
+    # 1600 x 40.  The splits whose vectors are the 40 rows of 1600 elements
+    # (left-to-right at the second bond, right-to-left at the first) take the
+    # global-memory round kernel (rows beyond 1024 elements, one wave per
+    # pair, one launch per round); the others (1600 vectors of 40 elements)
+    # the blocked path.  The cap truncates every step.
+    rng = np.random.default_rng(141)
+    mps = synth.random_mps(rng, 3, 40, 40)
+    mpo = synth.random_mpo(rng, 3, 40, 2)
+    ref = om.apply_simplify(mpo, mps, 24, 1e-12, sweeps=2)
+    out, err = ctx.mpo_apply(ctx.mpo_create(mpo), ctx.mps_create(mps), B.strategy(24, 1e-12, sweeps=2))
+    info = ctx.last_info()
+    deltas, ranks, _ = ctx.last_log()
+    got = out.read()
+    assert [1] + [t.shape[2] for t in got] == ref.ranks == [1, 24, 24, 1]
+    assert list(ranks) == ref.step_ranks
+    for k in range(len(ref.deltas)):
+        scale = ref.norms2[k] + ref.deltas[k]
+        assert abs(deltas[k] - ref.deltas[k]) <= 1e-10 * scale, k
+    assert abs(info["norm"] - ref.norm) <= 1e-12 * ref.norm
+    ab = om.scprod(got, ref.mps)
+    assert 1.0 - abs(ab) / math.sqrt(om.scprod(got, got) * om.scprod(ref.mps, ref.mps)) <= 1e-12
+    assert abs(err - ref.error_bound) <= 1e-6 * ref.error_bound + 1e-12
+    check_state(ctx, out, info)
